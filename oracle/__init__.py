@@ -1,0 +1,188 @@
+"""CPU oracle for fgemm -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the HIP implementation and never
+imports it.
+
+Contents
+--------
+* ``fgemm`` / ``fgemm_entries`` / ``freivalds`` / ``int_matmul`` / ``crt``:
+  ctypes wrappers around ``oracle.c`` (the plain definition of
+  C <- alpha*A*B + beta*C mod p, Section 3; 128-bit accumulation with a
+  reduction after every multiply-add).
+* ``oracle.bounds``: the paper's accumulation and growth bounds (eq. (1),
+  eq. (2), Theorem 3.1, Corollaries 3.2-3.4) in exact Python integers.
+* ``oracle.winograd``: Winograd's variant in exact Python integers (the
+  App. A formulas and the schedule table "tab:schedule:ABC"), with operation
+  counting and intermediate-magnitude tracking.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_libs = {}
+
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_I64 = ctypes.c_int64
+_U32 = ctypes.c_uint32
+_INT = ctypes.c_int
+
+
+def _load(plant=None):
+    key = plant
+    if key in _libs:
+        return _libs[key]
+    path = _build.lib_path(plant)
+    src = _build.SRC
+    if (not os.path.exists(path)) or os.path.getmtime(path) < os.path.getmtime(src):
+        _build.build(plant)
+    lib = ctypes.CDLL(path)
+    lib.oracle_fgemm.argtypes = [_U32, _INT, _INT, _I64, _I64, _I64, _U32,
+                                 ctypes.c_void_p, _I64, ctypes.c_void_p, _I64,
+                                 _U32, ctypes.c_void_p, _I64]
+    lib.oracle_fgemm.restype = _INT
+    lib.oracle_fgemm_entries.argtypes = [_U32, _INT, _INT, _I64, _U32,
+                                         ctypes.c_void_p, _I64, ctypes.c_void_p,
+                                         _I64, _U32, _I64, _i64p, _i64p, _u32p,
+                                         _u32p]
+    lib.oracle_fgemm_entries.restype = _INT
+    lib.oracle_freivalds.argtypes = [_U32, _INT, _INT, _I64, _I64, _I64, _U32,
+                                     ctypes.c_void_p, _I64, ctypes.c_void_p,
+                                     _I64, _U32, ctypes.c_void_p, _I64,
+                                     ctypes.c_void_p, _I64, _INT, _u32p, _u32p]
+    lib.oracle_freivalds.restype = _INT
+    lib.oracle_int_matmul.argtypes = [_I64, _I64, _I64, _i64p, _I64, _i64p,
+                                      _I64, _u64p, _i64p, _I64]
+    lib.oracle_int_matmul.restype = _INT
+    lib.oracle_crt.argtypes = [_INT, _u32p, _I64, _u32p, _u64p, _i64p]
+    lib.oracle_crt.restype = _INT
+    _libs[key] = lib
+    return lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.uint32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(trans, X, rows_op, cols_op):
+    """Leading dimension of X for op(X) of shape rows_op x cols_op."""
+    if X is None or X.size == 0:
+        return max(1, cols_op if not trans else rows_op)
+    return X.shape[1]
+
+
+def fgemm(p, A, B, C=None, alpha=1, beta=0, transA=False, transB=False,
+          plant=None):
+    """Return alpha*op(A)*op(B) + beta*C mod p as a new uint32 array.
+
+    A, B, C are 2-D uint32 arrays of residues in [0, p) (C may be None when
+    beta is 0).  op(X) = X.T when trans is set.
+    """
+    A = np.ascontiguousarray(A, dtype=np.uint32)
+    B = np.ascontiguousarray(B, dtype=np.uint32)
+    m = A.shape[1] if transA else A.shape[0]
+    k = A.shape[0] if transA else A.shape[1]
+    kb = B.shape[1] if transB else B.shape[0]
+    n = B.shape[0] if transB else B.shape[1]
+    if kb != k:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        out = np.zeros((m, n), dtype=np.uint32)
+    else:
+        out = np.array(C, dtype=np.uint32, copy=True, order="C")
+        if out.shape != (m, n):
+            raise ValueError("C has the wrong shape")
+    lda = max(1, A.shape[1]) if A.ndim == 2 else 1
+    ldb = max(1, B.shape[1]) if B.ndim == 2 else 1
+    rc = _load(plant).oracle_fgemm(int(p), int(bool(transA)), int(bool(transB)),
+                                   m, n, k, int(alpha) % int(p), _ptr(A), lda,
+                                   _ptr(B), ldb, int(beta) % int(p), _ptr(out),
+                                   max(1, n))
+    if rc != 0:
+        raise ValueError(f"oracle_fgemm rejected its arguments ({rc})")
+    return out
+
+
+def fgemm_entries(p, A, B, rows, cols, cin=None, alpha=1, beta=0,
+                  transA=False, transB=False):
+    """Sampled entries (rows[t], cols[t]) of alpha*op(A)*op(B) + beta*C mod p.
+
+    ``cin[t]`` is C at that position before the product (zeros if None)."""
+    A = np.ascontiguousarray(A, dtype=np.uint32)
+    B = np.ascontiguousarray(B, dtype=np.uint32)
+    k = A.shape[0] if transA else A.shape[1]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    if cin is None:
+        cin = np.zeros(rows.shape[0], dtype=np.uint32)
+    cin = np.ascontiguousarray(cin, dtype=np.uint32)
+    out = np.zeros(rows.shape[0], dtype=np.uint32)
+    rc = _load().oracle_fgemm_entries(int(p), int(bool(transA)),
+                                      int(bool(transB)), k, int(alpha) % int(p),
+                                      _ptr(A), A.shape[1], _ptr(B), B.shape[1],
+                                      int(beta) % int(p), rows.shape[0], rows,
+                                      cols, cin, out)
+    if rc != 0:
+        raise ValueError("oracle_fgemm_entries rejected its arguments")
+    return out
+
+
+def freivalds(p, A, B, C0, C1, X, alpha=1, beta=0, transA=False,
+              transB=False):
+    """Number of Freivalds trials (rows of X) on which C1 disagrees with
+    alpha*op(A)*op(B) + beta*C0 mod p.  0 means consistent."""
+    A = np.ascontiguousarray(A, dtype=np.uint32)
+    B = np.ascontiguousarray(B, dtype=np.uint32)
+    C0 = np.ascontiguousarray(C0, dtype=np.uint32)
+    C1 = np.ascontiguousarray(C1, dtype=np.uint32)
+    X = np.ascontiguousarray(X, dtype=np.uint32)
+    m = A.shape[1] if transA else A.shape[0]
+    k = A.shape[0] if transA else A.shape[1]
+    n = B.shape[0] if transB else B.shape[1]
+    work = np.zeros(k + 2 * m + 1, dtype=np.uint32)
+    rc = _load().oracle_freivalds(int(p), int(bool(transA)), int(bool(transB)),
+                                  m, n, k, int(alpha) % int(p), _ptr(A),
+                                  A.shape[1], _ptr(B), B.shape[1],
+                                  int(beta) % int(p), _ptr(C0), C0.shape[1],
+                                  _ptr(C1), C1.shape[1], X.shape[0], X, work)
+    if rc < 0:
+        raise ValueError("oracle_freivalds rejected its arguments")
+    return rc
+
+
+def int_matmul(A, B):
+    """Exact integer product of int64 matrices, as (lo uint64, hi int64)."""
+    A = np.ascontiguousarray(A, dtype=np.int64)
+    B = np.ascontiguousarray(B, dtype=np.int64)
+    m, k = A.shape
+    n = B.shape[1]
+    lo = np.zeros((m, n), dtype=np.uint64)
+    hi = np.zeros((m, n), dtype=np.int64)
+    rc = _load().oracle_int_matmul(m, n, k, A, k, B, n, lo, hi, n)
+    if rc != 0:
+        raise ValueError("oracle_int_matmul rejected its arguments")
+    return lo, hi
+
+
+def crt(primes, residues):
+    """Chinese remaindering of residue planes (list of equal-shape uint32
+    arrays, one per prime) into symmetric integers, as (lo, hi) words."""
+    primes = np.ascontiguousarray(primes, dtype=np.uint32)
+    shape = residues[0].shape
+    R = np.ascontiguousarray(np.stack([np.asarray(r, dtype=np.uint32).ravel()
+                                       for r in residues]))
+    count = R.shape[1]
+    lo = np.zeros(count, dtype=np.uint64)
+    hi = np.zeros(count, dtype=np.int64)
+    rc = _load().oracle_crt(len(primes), primes, count, R.ravel(), lo, hi)
+    if rc != 0:
+        raise ValueError("oracle_crt rejected its arguments")
+    return lo.reshape(shape), hi.reshape(shape)
