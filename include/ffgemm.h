@@ -1,0 +1,200 @@
+/*
+ * ffgemm.h -- C ABI of an MI355X (gfx950) library for exact matrix
+ * multiplication over Z/pZ with word-size moduli.
+ *
+ * The operation is the extended product of Dumas, Giorgi and Pernet,
+ * "Dense Linear Algebra over Word-Size Prime Fields: the FFLAS and FFPACK
+ * packages", Section 3 (the problem C <- alpha*A*B + beta*C of the Winograd
+ * schedule table "tab:schedule:ABC"):
+ *
+ *     C <- ( alpha * op(A) * op(B) + beta * C ) mod p.
+ *
+ * It is computed exactly: products are accumulated in machine arithmetic
+ * (binary64 on FP64 matrix cores, or int32 on INT8 matrix cores after a
+ * split of the residues into signed digits) and the reduction modulo p is
+ * delayed for as long as the accumulation bound of Section 2.1.2 (eq. (1),
+ * eq. (2)) allows; Winograd's variant (Section 3.2) may be applied on top,
+ * within the growth bound of Theorem 3.1.  Reduction modulo p is a ring
+ * homomorphism, so the result is unique and every path returns the same
+ * words.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Matrices are row-major.  op(A) is m x k: with transA == FF_NOTRANS, A is
+ * m x k with leading dimension lda >= k; with FF_TRANS it is k x m with
+ * lda >= m.  Likewise op(B) is k x n (B is k x n, ldb >= n, or n x k,
+ * ldb >= k).  C is m x n with ldc >= n.  Elements are uint32 residues in
+ * [0, p); outputs are canonical residues in [0, p).  2 <= p < 2^31; p need
+ * not be prime (only ring operations are used).
+ *
+ * A, B and C are device pointers owned by the caller (for instance the
+ * storage of torch tensors); the library never frees them.  Input entries
+ * must be < p: this is not checked unless ff_opts.validate is set (then an
+ * out-of-range entry yields FF_EINVAL and nothing is written).  When
+ * beta == 0 (mod p) C is write-only and may hold anything.
+ *
+ * Calls are asynchronous: the work is enqueued on a HIP stream (the one of
+ * ff_set_stream, or ff_opts.stream) and the call returns; completion is
+ * observed through that stream.  Work enqueued on one stream runs in order;
+ * two calls on different streams must not share output memory.
+ *
+ * Errors are returned as ff_status codes; no entry point aborts or exits,
+ * and on error nothing is enqueued.  ff_last_error() gives a description of
+ * the last failure of the calling thread.
+ */
+#ifndef FFGEMM_H
+#define FFGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FF_OK = 0,
+    FF_EINVAL = -1,        /* bad argument (dimension, leading dimension, p, null pointer, entry >= p) */
+    FF_EUNSUPPORTED = -2,  /* valid, but the requested path cannot compute it exactly */
+    FF_ENOMEM = -3,        /* workspace allocation failed */
+    FF_EHIP = -4,          /* a HIP runtime call failed */
+    FF_EBUSY = -5,         /* a server request can never fit its memory budget */
+    FF_ENOTFOUND = -6      /* unknown request id */
+} ff_status;
+
+enum { FF_NOTRANS = 0, FF_TRANS = 1 };
+
+/* Arithmetic path.  FP64: centered residues as doubles on FP64 matrix
+ * cores, reduction every kblock products (Section 2.1.2, eq. (2), read with
+ * the binary64 exactness limit 2^53).  INT8: centered residues split into
+ * signed digits, digit products on INT8 matrix cores with int32 sums,
+ * recombined modulo p in the epilogue. */
+enum { FF_PATH_AUTO = 0, FF_PATH_FP64 = 1, FF_PATH_INT8 = 2 };
+
+typedef struct ff_opts {
+    int path;            /* FF_PATH_*                                              */
+    int winograd_levels; /* 0..3 recursive levels of Winograd's variant (Section
+                            3.2); -1: automatic, l = floor(log2(n/w)) + 1 with the
+                            crossover order w of Section 3.2.1 (clamped at 0)      */
+    int digit_bits;      /* INT8 path digit width, 7 or 8; 0: automatic            */
+    int validate;        /* nonzero: check that inputs are residues < p first
+                            (makes the call synchronous)                           */
+    int preadd_mode;     /* Winograd pre-additions: 0 automatic; 1 delayed (kept as
+                            unreduced integers, the form Theorem 3.1 bounds); 2
+                            reduced to centered residues at the leaves             */
+    void *stream;        /* hipStream_t to enqueue on; NULL: the ff_set_stream one */
+} ff_opts;
+
+/* What a call will do (ff_plan_query).  Host-only; no device is touched. */
+typedef struct ff_plan_info {
+    int path;                /* FF_PATH_FP64 or FF_PATH_INT8                        */
+    int winograd_levels;     /* levels actually applied                             */
+    int preadds_reduced;     /* 1 if Winograd leaf operands are reduced mod p       */
+    int digit_bits;          /* INT8: 7 or 8; FP64: 0                               */
+    int slices;              /* INT8: digits per operand; FP64: 0                   */
+    int64_t operand_lo;      /* range of the values entering the products: the      */
+    int64_t operand_hi;      /*  centered residues, widened by Winograd pre-additions */
+    int64_t max_abs_product; /* bound on one product term |a*b| at the leaves       */
+    int64_t kblock;          /* FP64: products summed between two reductions;
+                                INT8: largest K of one exact int32 pass             */
+    int64_t workspace_bytes; /* device workspace the call needs                     */
+    int tile_config;         /* kernel tile configuration id                        */
+} ff_plan_info;
+
+/* One fgemm of a batch or a server request: same meaning as the arguments
+ * of ff_fgemm. */
+typedef struct ff_job {
+    uint32_t p;
+    int transA, transB;
+    int64_t m, n, k;
+    uint32_t alpha, beta;
+    const uint32_t *A;
+    int64_t lda;
+    const uint32_t *B;
+    int64_t ldb;
+    uint32_t *C;
+    int64_t ldc;
+} ff_job;
+
+/* Checks that a gfx950 device is current and sets up per-device state.
+ * Optional: every entry point initialises lazily. */
+int ff_init(void);
+
+/* Releases the library's device workspaces and cached plans. */
+int ff_finalize(void);
+
+/* Sets the stream later calls enqueue on (hipStream_t; NULL = null stream),
+ * for the calling thread. */
+int ff_set_stream(void *hip_stream);
+
+/* C <- (alpha*op(A)*op(B) + beta*C) mod p, automatic path (Section 3).
+ * BLAS quick returns: m == 0 or n == 0 does nothing; k == 0 or
+ * alpha == 0 (mod p) gives C <- beta*C mod p. */
+int ff_fgemm(uint32_t p, int transA, int transB,
+             int64_t m, int64_t n, int64_t k,
+             uint32_t alpha, const uint32_t *A, int64_t lda,
+             const uint32_t *B, int64_t ldb,
+             uint32_t beta, uint32_t *C, int64_t ldc);
+
+/* Same, with explicit options (NULL opts = automatic). */
+int ff_fgemm_ex(uint32_t p, int transA, int transB,
+                int64_t m, int64_t n, int64_t k,
+                uint32_t alpha, const uint32_t *A, int64_t lda,
+                const uint32_t *B, int64_t ldb,
+                uint32_t beta, uint32_t *C, int64_t ldc,
+                const ff_opts *opts);
+
+/* The plan ff_fgemm_ex would follow for these sizes (host-only). */
+int ff_plan_query(uint32_t p, int transA, int transB,
+                  int64_t m, int64_t n, int64_t k,
+                  const ff_opts *opts, ff_plan_info *out);
+
+/* Runs njobs independent fgemms (each with its own p, sizes, pointers) as
+ * one persistent launch over a shared tile queue, preceded by one digit
+ * slicing launch for the whole batch (INT8 path).  Outputs must not
+ * overlap.  This is the multi-modular workload of the Chinese remaindering
+ * approach (Sections 1 and 7). */
+int ff_fgemm_batched(const ff_job *jobs, int njobs, const ff_opts *opts);
+
+/* Captures the launches of a batch into a HIP graph bound to the given
+ * pointers, for repeated replay with one launch call.  *graph receives an
+ * opaque handle. */
+int ff_batch_graph_create(const ff_job *jobs, int njobs, const ff_opts *opts,
+                          void **graph);
+int ff_batch_graph_launch(void *graph, void *hip_stream);
+int ff_batch_graph_destroy(void *graph);
+
+/* Serving loop.  A server owns a device arena of hbm_budget_bytes for the
+ * workspaces of its requests and a thread that admits queued requests while
+ * their footprint fits, merges them into persistent batched launches and
+ * retires them on completion (continuous batching).  Request matrices stay
+ * device-resident and caller-owned until the request is done.  submit
+ * returns FF_EBUSY only for a request that can never fit the budget. */
+int ff_server_create(int64_t hbm_budget_bytes, const ff_opts *opts, void **server);
+int ff_server_submit(void *server, const ff_job *job, uint64_t *id);
+int ff_server_poll(void *server, uint64_t id, int *done);
+int ff_server_wait(void *server, uint64_t id);
+/* Latency (submit to completion) percentiles in ms over finished requests,
+ * and throughput in Gop/s (sum of 2mnk over the busy interval). */
+int ff_server_stats(void *server, double *p50_ms, double *p99_ms, double *gops,
+                    int64_t *completed, int64_t *max_inflight);
+int ff_server_destroy(void *server);
+
+/* Kernel timing for measurement.  While enabled, every launch of the
+ * matrix-core kernels (FP64 and INT8 fgemm, single or batched) is bracketed
+ * by a HIP event pair recorded on the stream it is launched on, and so is
+ * every digit-slicing launch.  ff_profile_read synchronises those events
+ * and returns the summed durations (ms) and launch counts since the last
+ * enable or read, then clears them.  Not thread-safe against concurrent
+ * fgemm calls; meant for benchmarks. */
+int ff_profile_enable(int on);
+int ff_profile_read(double *gemm_ms, int64_t *gemm_launches,
+                    double *slice_ms, int64_t *slice_launches);
+
+/* Thread-local text of the last non-OK status. */
+const char *ff_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFGEMM_H */

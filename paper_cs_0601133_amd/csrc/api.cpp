@@ -1,0 +1,366 @@
+// C ABI entry points: argument checks, quick returns, workspace, dispatch to
+// the FP64 or INT8 path (with or without Winograd levels).
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ff_internal.h"
+#include "ff_profile.h"
+#include "ff_runtime.h"
+
+namespace ff {
+
+namespace {
+thread_local std::string g_err;
+thread_local hipStream_t g_stream = nullptr;
+} // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+int fail(int status, const std::string &msg)
+{
+    g_err = msg;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// Per-device state
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Buffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct DevState {
+    std::mutex mu;
+    bool checked = false;
+    bool ok = false;
+    std::string arch;
+    std::map<hipStream_t, Buffer> ws;
+};
+
+std::mutex g_mu;
+std::map<int, DevState *> g_devs;
+
+} // namespace
+
+
+int check_device()
+{
+    int dev = 0;
+    FF_HIP_CHECK(hipGetDevice(&dev));
+    DevState *ds;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_devs.find(dev);
+        if (it == g_devs.end()) it = g_devs.emplace(dev, new DevState()).first;
+        ds = it->second;
+    }
+    std::lock_guard<std::mutex> lk(ds->mu);
+    if (!ds->checked) {
+        hipDeviceProp_t prop;
+        FF_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+        ds->arch = prop.gcnArchName;
+        ds->ok = ds->arch.rfind("gfx950", 0) == 0;
+        ds->checked = true;
+    }
+    if (!ds->ok)
+        return fail(FF_EUNSUPPORTED, "device " + std::to_string(dev) + " is " + ds->arch +
+                                         "; this library is built for gfx950 only");
+    return FF_OK;
+}
+
+// Grow-only workspace per (device, stream).  Calls on one stream run in
+// order, so reusing its workspace is safe; before a buffer is replaced the
+// stream is drained.
+int workspace(hipStream_t st, size_t bytes, void **out)
+{
+    int dev = 0;
+    FF_HIP_CHECK(hipGetDevice(&dev));
+    DevState *ds;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ds = g_devs[dev];
+    }
+    std::lock_guard<std::mutex> lk(ds->mu);
+    Buffer &b = ds->ws[st];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            FF_HIP_CHECK(hipStreamSynchronize(st));
+            FF_HIP_CHECK(hipFree(b.ptr));
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = std::max<size_t>(bytes, size_t(1) << 20);
+        if (hipMalloc(&b.ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            b.ptr = nullptr;
+            return fail(FF_ENOMEM, "workspace allocation of " + std::to_string(want) +
+                                       " bytes failed");
+        }
+        b.bytes = want;
+    }
+    *out = b.ptr;
+    return FF_OK;
+}
+
+int release_all()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_devs) {
+        DevState *ds = kv.second;
+        std::lock_guard<std::mutex> lk2(ds->mu);
+        for (auto &w : ds->ws) {
+            if (w.second.ptr) {
+                (void)hipStreamSynchronize(w.first);
+                (void)hipFree(w.second.ptr);
+            }
+        }
+        ds->ws.clear();
+    }
+    return FF_OK;
+}
+
+hipStream_t stream_of(const ff_opts *o)
+{
+    if (o && o->stream) return (hipStream_t)o->stream;
+    return g_stream;
+}
+
+void set_stream(hipStream_t s) { g_stream = s; }
+
+ff_opts default_opts()
+{
+    ff_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.winograd_levels = -1;
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks shared by the single and batched entry points
+// ---------------------------------------------------------------------------
+int check_args(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+               const uint32_t *A, int64_t lda, const uint32_t *B, int64_t ldb,
+               const uint32_t *C, int64_t ldc)
+{
+    if (p < 2 || p > 0x7FFFFFFFu) return fail(FF_EINVAL, "p must satisfy 2 <= p < 2^31");
+    if ((transA != 0 && transA != 1) || (transB != 0 && transB != 1))
+        return fail(FF_EINVAL, "transA/transB must be FF_NOTRANS or FF_TRANS");
+    if (m < 0 || n < 0 || k < 0) return fail(FF_EINVAL, "negative dimension");
+    const int64_t DMAX = int64_t(1) << 30;
+    if (m > DMAX || n > DMAX || k > DMAX) return fail(FF_EINVAL, "dimension exceeds 2^30");
+    if (m == 0 || n == 0) return FF_OK;
+    if (ldc < n) return fail(FF_EINVAL, "ldc < n");
+    if (!C) return fail(FF_EINVAL, "C is null");
+    if (k > 0) {
+        if (lda < (transA ? m : k)) return fail(FF_EINVAL, "lda too small");
+        if (ldb < (transB ? k : n)) return fail(FF_EINVAL, "ldb too small");
+        if (!A || !B) return fail(FF_EINVAL, "A or B is null");
+    }
+    return FF_OK;
+}
+
+// alpha * R^t mod p, t = 0 .. 2S-2.
+void digit_weights(uint32_t p, uint32_t alpha, int bits, int S, uint32_t *w)
+{
+    const uint64_t R = (uint64_t(1) << bits) % p;
+    uint64_t x = alpha % p;
+    for (int t = 0; t < 2 * S - 1; ++t) {
+        w[t] = (uint32_t)x;
+        x = (x * R) % p;
+    }
+}
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// ---------------------------------------------------------------------------
+// Plain (no Winograd) paths
+// ---------------------------------------------------------------------------
+int run_f64_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                  uint32_t alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
+                  uint32_t beta, uint32_t *C, int64_t ldc, int in_mode, int64_t kblock,
+                  hipStream_t st)
+{
+    F64Job J;
+    std::memset(&J, 0, sizeof(J));
+    J.A = A; J.B = B; J.C = C;
+    J.lda = lda; J.ldb = ldb; J.ldc = ldc;
+    J.m = (int)m; J.n = (int)n; J.k = (int)k;
+    J.transA = transA; J.transB = transB; J.in_mode = in_mode;
+    J.p = p; J.alpha = alpha; J.beta = beta;
+    J.pd = (double)p; J.pinv = 1.0 / (double)p;
+    J.fold_every = (int)std::min<int64_t>(kblock / 4, 0x3FFFFFFF);
+    J.tiles_m = (int)((m + F64_BM - 1) / F64_BM);
+    J.tiles_n = (int)((n + F64_BN - 1) / F64_BN);
+    FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_f64(J, st)));
+    return FF_OK;
+}
+
+// Describes the slicing of an operand into packed digit planes.
+SliceJob slice_job(const void *X, int64_t ldx, int rows, int K, int trans, int in_mode,
+                   uint32_t p, int S, int bits, int8_t *D, int RT, int KP)
+{
+    SliceJob s;
+    std::memset(&s, 0, sizeof(s));
+    s.X = X; s.ldx = ldx; s.rows = rows; s.K = K; s.trans = trans; s.in_mode = in_mode;
+    s.p = p; s.S = S; s.bits = bits; s.D = D; s.RT = RT;
+    s.rows_pad = (int)round_up(std::max(rows, 1), RT);
+    s.KP = KP;
+    s.plane = (int64_t)s.rows_pad * KP;
+    return s;
+}
+
+int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                 uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
+                 int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const Plan &P,
+                 void *ws, hipStream_t st)
+{
+    const I8Tile t = i8_tile_for(P.slices);
+    const int64_t kpass = std::min<int64_t>(k, P.kblock);
+    const int KP = (int)round_up(kpass, I8_BK);
+    const int mp = (int)round_up(m, t.bm()), np = (int)round_up(n, t.bn());
+    int8_t *Ad = (int8_t *)ws;
+    int8_t *Bd = Ad + (int64_t)P.slices * mp * KP;
+    for (int64_t k0 = 0; k0 < k; k0 += kpass) {
+        const int kc = (int)std::min<int64_t>(kpass, k - k0);
+        const int KPc = (int)round_up(kc, I8_BK);
+        // A: rows m, element (i, l) of op(A)
+        const uint32_t *Ak = transA ? A + k0 * lda : A + k0;
+        SliceJob sa = slice_job(Ak, lda, (int)m, kc, transA, IN_RESIDUE, p, P.slices, P.bits,
+                                Ad, t.bm(), KPc);
+        // B^T: rows n, element (j, l) = op(B)(l, j)
+        const uint32_t *Bk = transB ? B + k0 : B + k0 * ldb;
+        SliceJob sb = slice_job(Bk, ldb, (int)n, kc, transB ? 0 : 1, IN_RESIDUE, p, P.slices,
+                                P.bits, Bd, t.bn(), KPc);
+        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_slice(sa, st)));
+        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_slice(sb, st)));
+        I8Job J;
+        std::memset(&J, 0, sizeof(J));
+        J.Ad = Ad; J.Bd = Bd; J.a_plane = sa.plane; J.b_plane = sb.plane;
+        J.C = C; J.ldc = ldc; J.m = (int)m; J.n = (int)n; J.KP = KPc; J.s = P.slices;
+        J.p = p; J.beta = k0 == 0 ? beta : 1u;
+        J.pd = (double)p; J.pinv = 1.0 / (double)p;
+        digit_weights(p, alpha, P.slices == 1 ? 8 : P.bits, P.slices, J.w);
+        J.tiles_m = mp / t.bm(); J.tiles_n = np / t.bn();
+        FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_i8(P.slices, J, st)));
+    }
+    return FF_OK;
+}
+
+int validate_inputs(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                    const uint32_t *A, int64_t lda, const uint32_t *B, int64_t ldb,
+                    uint32_t beta, const uint32_t *C, int64_t ldc, hipStream_t st)
+{
+    unsigned *bad = nullptr;
+    FF_HIP_CHECK(hipMalloc(&bad, sizeof(unsigned)));
+    unsigned h = 0;
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned), st);
+    if (e == hipSuccess && k > 0) {
+        e = launch_validate(A, lda, transA ? k : m, transA ? m : k, p, bad, st);
+        if (e == hipSuccess) e = launch_validate(B, ldb, transB ? n : k, transB ? k : n, p, bad, st);
+    }
+    if (e == hipSuccess && beta) e = launch_validate(C, ldc, m, n, p, bad, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return fail(FF_EHIP, std::string("validate: ") + hipGetErrorString(e));
+    if (h) return fail(FF_EINVAL, std::to_string(h) + " input entries are not residues < p");
+    return FF_OK;
+}
+
+} // namespace ff
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace ff;
+
+extern "C" {
+
+int ff_init(void) { return check_device(); }
+
+int ff_finalize(void) { return release_all(); }
+
+int ff_set_stream(void *hip_stream)
+{
+    set_stream((hipStream_t)hip_stream);
+    return FF_OK;
+}
+
+const char *ff_last_error(void) { return g_err.c_str(); }
+
+int ff_plan_query(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                  const ff_opts *opts, ff_plan_info *out)
+{
+    if (!out) return fail(FF_EINVAL, "out is null");
+    if ((transA != 0 && transA != 1) || (transB != 0 && transB != 1))
+        return fail(FF_EINVAL, "transA/transB must be FF_NOTRANS or FF_TRANS");
+    if (m < 0 || n < 0 || k < 0) return fail(FF_EINVAL, "negative dimension");
+    ff_opts o = opts ? *opts : default_opts();
+    Plan P;
+    int rc = make_plan(p, m, n, k, o, &P);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->path = P.path;
+    out->winograd_levels = P.levels;
+    out->preadds_reduced = P.preadds_reduced;
+    out->digit_bits = P.path == FF_PATH_INT8 ? P.bits : 0;
+    out->slices = P.path == FF_PATH_INT8 ? P.slices : 0;
+    out->operand_lo = P.lo;
+    out->operand_hi = P.hi;
+    out->max_abs_product = P.max_prod;
+    out->kblock = P.kblock;
+    out->workspace_bytes = P.ws_bytes;
+    out->tile_config = P.tile;
+    return FF_OK;
+}
+
+int ff_fgemm_ex(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
+                int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const ff_opts *opts)
+{
+    int rc = check_args(p, transA, transB, m, n, k, A, lda, B, ldb, C, ldc);
+    if (rc) return rc;
+    if (m == 0 || n == 0) return FF_OK;
+    ff_opts o = opts ? *opts : default_opts();
+    if ((rc = check_device())) return rc;
+    hipStream_t st = stream_of(&o);
+    alpha %= p;
+    beta %= p;
+    if (o.validate) {
+        rc = validate_inputs(p, transA, transB, m, n, k, A, lda, B, ldb, beta, C, ldc, st);
+        if (rc) return rc;
+    }
+    if (k == 0 || alpha == 0) {
+        if (beta == 1) return FF_OK;
+        FF_HIP_CHECK(launch_scale(C, ldc, m, n, p, beta, st));
+        return FF_OK;
+    }
+    Plan P;
+    if ((rc = make_plan(p, m, n, k, o, &P))) return rc;
+    if (P.levels > 0)
+        return run_winograd(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                            P, o, st);
+    if (P.path == FF_PATH_FP64)
+        return run_f64_plain(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                             IN_RESIDUE, P.kblock, st);
+    void *ws = nullptr;
+    if ((rc = workspace(st, (size_t)P.ws_bytes, &ws))) return rc;
+    return run_i8_plain(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, P,
+                        ws, st);
+}
+
+int ff_fgemm(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+             uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B, int64_t ldb,
+             uint32_t beta, uint32_t *C, int64_t ldc)
+{
+    return ff_fgemm_ex(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                       nullptr);
+}
+
+} // extern "C"

@@ -1,0 +1,186 @@
+// Internal declarations of the fgemm library: plans, job descriptors shared
+// by host code and kernels, kernel launchers.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/ffgemm.h"
+
+namespace ff {
+
+// ---------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+#define FF_HIP_CHECK(expr)                                                    \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return ::ff::fail(FF_EHIP, std::string(#expr) + ": " +           \
+                                           hipGetErrorString(e_));            \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Tile configurations
+// ---------------------------------------------------------------------------
+// FP64 kernel: 128 x 128 output tile per workgroup of 256 threads, K step 16.
+constexpr int F64_BM = 128, F64_BN = 128, F64_BK = 16, F64_THREADS = 256;
+
+// INT8 kernel: workgroup tile BM x BN, K step 64 bytes, waves of 64 lanes
+// each owning (32*TM) x (32*TN) outputs.  One configuration per slice count.
+struct I8Tile {
+    int S;      // digits per operand (compile-time in the kernel)
+    int TM, TN; // 32x32 MFMA tiles per wave
+    int WGM, WGN;
+    int bm() const { return WGM * 32 * TM; }
+    int bn() const { return WGN * 32 * TN; }
+    int threads() const { return 64 * WGM * WGN; }
+};
+I8Tile i8_tile_for(int S);
+constexpr int I8_BK = 64;
+
+// ---------------------------------------------------------------------------
+// Plan (the host-side decisions of one call)
+// ---------------------------------------------------------------------------
+struct Plan {
+    int path = FF_PATH_INT8;
+    int levels = 0;
+    int preadds_reduced = 0; // Winograd pre-additions reduced to centered residues
+    int bits = 0;            // INT8 digit width
+    int slices = 0;          // INT8 digits per operand
+    int64_t lo = 0, hi = 0;  // range of leaf operands
+    int64_t max_prod = 0;    // bound on |a*b| of one leaf product term
+    int64_t kblock = 0;      // FP64: products between folds; INT8: K per pass
+    int tile = 0;
+    int64_t ws_bytes = 0;
+    // leaf problem shape (after peeling the top level to multiples of 2^L)
+    int64_t me = 0, ne = 0, ke = 0;
+};
+
+// Fills *pl for the given problem.  Returns FF_OK or an error status (with
+// the message set).  Pure host code.
+int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
+              Plan *pl);
+
+// Centered range of residues modulo p: [-(p/2), (p-1)/2].
+inline int64_t centered_lo(uint32_t p) { return -(int64_t)(p / 2); }
+inline int64_t centered_hi(uint32_t p) { return (int64_t)((p - 1) / 2); }
+
+// ---------------------------------------------------------------------------
+// Device job descriptors
+// ---------------------------------------------------------------------------
+// Operand of the FP64 kernel: uint32 residues centered on load, or int32
+// values already centered (Winograd leaves).
+enum { IN_RESIDUE = 0, IN_SIGNED = 1 };
+
+struct F64Job {
+    const void *A;
+    const void *B;
+    uint32_t *C;
+    int64_t lda, ldb, ldc;
+    int m, n, k;
+    int transA, transB, in_mode;
+    uint32_t p, alpha, beta;
+    double pd, pinv;
+    int fold_every;  // MFMA k-substeps (4 products each) between reductions
+    int tiles_m, tiles_n;
+    int tile_start;  // first global tile index of this job (batched launches)
+};
+
+// Slicing task: one operand of one job into packed digit planes.
+struct SliceJob {
+    const void *X;      // uint32 residues or int32 signed values
+    int64_t ldx;
+    int rows, K;        // logical operand: rows x K (A: m x k, B^T: n x k)
+    int trans;          // element (r, c) at X[c*ldx + r] instead of X[r*ldx + c]
+    int in_mode;        // IN_RESIDUE (center with p) or IN_SIGNED
+    uint32_t p;
+    int S, bits;
+    int8_t *D;          // packed planes
+    int RT;             // row tile of the packing
+    int rows_pad, KP;   // padded sizes
+    int64_t plane;      // bytes per digit plane = rows_pad * KP
+    int block_start;    // first global block of this task
+};
+
+// INT8 GEMM job on packed digit planes.
+struct I8Job {
+    const int8_t *Ad;
+    const int8_t *Bd;
+    int64_t a_plane, b_plane;
+    uint32_t *C;
+    int64_t ldc;
+    int m, n, KP;
+    int s;              // digits of this job (<= kernel's S)
+    uint32_t p, beta;
+    double pd, pinv;
+    uint32_t w[9];      // alpha * R^t mod p, t = 0 .. 2s-2
+    int tiles_m, tiles_n;
+    int tile_start;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+// Single-job FP64 fgemm: job passed by value.
+hipError_t launch_f64(const F64Job &job, hipStream_t st);
+// Batched FP64: device job table; grid = total tiles (persistent == 0) or a
+// persistent grid draining a tile counter (ctr: 2 words, zero on entry, left
+// at zero on exit).
+hipError_t launch_f64_batched(const F64Job *dev_jobs, int njobs, int total_tiles,
+                              int persistent, unsigned *ctr, hipStream_t st);
+
+hipError_t launch_slice(const SliceJob &job, hipStream_t st);
+hipError_t launch_slice_batched(const SliceJob *dev_jobs, int njobs,
+                                int total_blocks, hipStream_t st);
+
+hipError_t launch_i8(int S, const I8Job &job, hipStream_t st);
+hipError_t launch_i8_batched(int S, const I8Job *dev_jobs, int njobs,
+                             int total_tiles, int persistent, unsigned *ctr,
+                             hipStream_t st);
+
+// C <- beta*C mod p (beta == 0: C <- 0), m x n, ldc.
+hipError_t launch_scale(uint32_t *C, int64_t ldc, int64_t m, int64_t n,
+                        uint32_t p, uint32_t beta, hipStream_t st);
+
+// Counts entries >= p of an m x n (ld) uint32 matrix into *bad (device).
+hipError_t launch_validate(const uint32_t *X, int64_t ld, int64_t rows,
+                           int64_t cols, uint32_t p, unsigned *bad,
+                           hipStream_t st);
+
+// Winograd pre-additions of one operand over L levels (see winograd.cpp).
+struct PreaddJob {
+    const uint32_t *X;   // residues, logical rows x cols of op(X)
+    int64_t ldx;
+    int trans;
+    int rows, cols;      // leaf block size: (full rows) / 2^L, (full cols) / 2^L
+    int L;
+    int side;            // 0: A-side combinations, 1: B-side
+    int reduce;          // reduce each leaf value to a centered residue
+    uint32_t p;
+    int out_digits;      // 0: write int32 leaves, 1: write packed digit planes
+    int32_t *Y;          // int32 leaves: [7^L][rows][cols]
+    // digit output (out_digits): planes of leaf q at D + q * leaf_bytes
+    int8_t *D;
+    int64_t leaf_bytes;
+    int S, bits, RT, rows_pad, KP;
+    int64_t plane;
+    int transpose_out;   // B side: leaves stored transposed (cols x rows)
+};
+hipError_t launch_preadd(const PreaddJob &job, hipStream_t st);
+
+struct PostaddJob {
+    const uint32_t *P;   // 7^L leaf products, each rows x cols, ld = cols
+    int rows, cols, L;
+    uint32_t *C;
+    int64_t ldc;
+    uint32_t p, alpha, beta;
+    double pd, pinv;
+};
+hipError_t launch_postadd(const PostaddJob &job, hipStream_t st);
+
+} // namespace ff

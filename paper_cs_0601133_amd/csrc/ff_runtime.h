@@ -1,0 +1,37 @@
+// Host-side helpers shared by the C ABI, the Winograd driver, the batched
+// launcher and the server.  Not part of the C ABI.
+#pragma once
+
+#include "ff_internal.h"
+
+namespace ff {
+
+int check_device();
+int workspace(hipStream_t st, size_t bytes, void **out);
+int release_all();
+hipStream_t stream_of(const ff_opts *o);
+void set_stream(hipStream_t s);
+ff_opts default_opts();
+int check_args(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+               const uint32_t *A, int64_t lda, const uint32_t *B, int64_t ldb,
+               const uint32_t *C, int64_t ldc);
+void digit_weights(uint32_t p, uint32_t alpha, int bits, int S, uint32_t *w);
+int64_t round_up(int64_t x, int64_t q);
+SliceJob slice_job(const void *X, int64_t ldx, int rows, int K, int trans, int in_mode,
+                   uint32_t p, int S, int bits, int8_t *D, int RT, int KP);
+int slice_blocks(const SliceJob &J);
+int run_f64_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                  uint32_t alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
+                  uint32_t beta, uint32_t *C, int64_t ldc, int in_mode, int64_t kblock,
+                  hipStream_t st);
+int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                 uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
+                 int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const Plan &P,
+                 void *ws, hipStream_t st);
+// Winograd levels > 0 (winograd.cpp).
+int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                 uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
+                 int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const Plan &P,
+                 const ff_opts &o, hipStream_t st);
+
+} // namespace ff

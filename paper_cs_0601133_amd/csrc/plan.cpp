@@ -1,0 +1,248 @@
+// Planner: the host-side decisions of one fgemm call.
+//
+// * Centered residues (Section 2.1.2: the balanced representation halves
+//   the accumulation bound).  For modulus p they lie in [-(p/2), (p-1)/2].
+// * Winograd levels (Section 3.2.1): l = floor(log2(n/w)) + 1 for the
+//   crossover order w, clamped at 0, or as requested.  Each level's
+//   pre-additions widen the operand range; with unreduced pre-additions (the
+//   delayed form Theorem 3.1 analyses) the widest leaf operand after l levels
+//   and the largest leaf product term follow from interval arithmetic over
+//   the coefficient tables below.  The leaf product term bound equals
+//   v_l^A v_l^B of Theorem 3.1.
+// * FP64 path: kblock = largest kb with kb * max|a*b| + carry <= 2^53, the
+//   binary64 exactness limit (eq. (2) read with gamma = 53 and the residue
+//   carried between blocks, carry = p + 2, which bounds |x - p*rint(x/p)|
+//   after one floating-point-inverse reduction).
+// * INT8 path: the smallest number S of signed digits (7- or 8-bit) that
+//   covers the operand range; int32 K-block = floor((2^31-1) / (S dA dB))
+//   since one accumulator sums the S digit pairs of equal weight.
+#include <algorithm>
+#include <cstdlib>
+#include <vector>
+
+#include "ff_internal.h"
+
+namespace ff {
+
+I8Tile i8_tile_for(int S)
+{
+    switch (S) {
+    case 1: return I8Tile{1, 2, 2, 2, 2}; // 128 x 128, 1 accumulator set
+    case 2: return I8Tile{2, 2, 2, 2, 2}; // 128 x 128, 3 sets
+    case 3: return I8Tile{3, 1, 2, 4, 1}; // 128 x 64, 5 sets
+    case 4: return I8Tile{4, 1, 2, 4, 1}; // 128 x 64, 7 sets
+    default: return I8Tile{5, 1, 1, 4, 1}; // 128 x 32, 9 sets
+    }
+}
+
+namespace {
+
+constexpr int64_t TWO53 = int64_t(1) << 53;
+constexpr int64_t I32MAX = 2147483647;
+
+// Coefficients of the seven leaf operands of one Winograd level on the four
+// quadrants (11, 12, 21, 22), products P1..P7 (Appendix A).
+const int PRE_A[7][4] = {
+    {1, 0, 0, 0},   // A11
+    {0, 1, 0, 0},   // A12
+    {1, 1, -1, -1}, // S4 = A12 - (A21 + A22 - A11)
+    {0, 0, 0, 1},   // A22
+    {0, 0, 1, 1},   // S1 = A21 + A22
+    {-1, 0, 1, 1},  // S2 = S1 - A11
+    {1, 0, -1, 0},  // S3 = A11 - A21
+};
+const int PRE_B[7][4] = {
+    {1, 0, 0, 0},   // B11
+    {0, 0, 1, 0},   // B21
+    {0, 0, 0, 1},   // B22
+    {1, -1, -1, 1}, // T4 = T2 - B21
+    {-1, 1, 0, 0},  // T1 = B12 - B11
+    {1, -1, 0, 1},  // T2 = B22 - T1
+    {0, -1, 0, 1},  // T3 = B22 - B12
+};
+
+struct Range { int64_t lo, hi; };
+
+Range combine(const int *c, Range x)
+{
+    Range r{0, 0};
+    for (int q = 0; q < 4; ++q) {
+        if (c[q] > 0) { r.lo += c[q] * x.lo; r.hi += c[q] * x.hi; }
+        else if (c[q] < 0) { r.lo += c[q] * x.hi; r.hi += c[q] * x.lo; }
+    }
+    return r;
+}
+
+int64_t mag(Range r) { return std::max(-r.lo, r.hi); }
+
+void leaf_bounds(Range base, int L, Range *widest, int64_t *max_prod)
+{
+    std::vector<std::pair<Range, Range>> cur{{base, base}}, nxt;
+    for (int l = 0; l < L; ++l) {
+        nxt.clear();
+        for (auto &pr : cur)
+            for (int q = 0; q < 7; ++q)
+                nxt.push_back({combine(PRE_A[q], pr.first),
+                               combine(PRE_B[q], pr.second)});
+        cur.swap(nxt);
+    }
+    Range w{0, 0};
+    int64_t mp = 0;
+    for (auto &pr : cur) {
+        w.lo = std::min({w.lo, pr.first.lo, pr.second.lo});
+        w.hi = std::max({w.hi, pr.first.hi, pr.second.hi});
+        mp = std::max(mp, mag(pr.first) * mag(pr.second));
+    }
+    *widest = w;
+    *max_prod = mp;
+}
+
+// Smallest number of signed digits of the given width covering [lo, hi];
+// one direct int8 plane when the range fits int8.  0 if more than 5.
+int slices_for(Range r, int bits)
+{
+    if (r.lo >= -128 && r.hi <= 127) return 1;
+    const int64_t R = int64_t(1) << bits;
+    int64_t geo = 1, pw = 1;
+    for (int s = 1; s <= 5; ++s) {
+        // s digits in [-R/2, R/2 - 1] cover [-(R/2) geo, (R/2 - 1) geo]
+        if (-(R / 2) * geo <= r.lo && r.hi <= (R / 2 - 1) * geo) return s;
+        pw *= R;
+        geo += pw;
+    }
+    return 0;
+}
+
+int64_t digit_mag(Range r, int bits, int S)
+{
+    if (S == 1 && r.lo >= -128 && r.hi <= 127) return mag(r);
+    return int64_t(1) << (bits - 1);
+}
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+int64_t ipow7(int L) { int64_t r = 1; while (L--) r *= 7; return r; }
+
+int crossover_w()
+{
+    const char *e = std::getenv("FF_WINOGRAD_W");
+    if (e && std::atoi(e) > 0) return std::atoi(e);
+    return 16384;
+}
+
+} // namespace
+
+int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
+              Plan *pl)
+{
+    Plan P;
+    if (p < 2 || p > 0x7FFFFFFFu)
+        return fail(FF_EINVAL, "modulus p must satisfy 2 <= p < 2^31");
+    if (o.path < 0 || o.path > 2)
+        return fail(FF_EINVAL, "unknown path");
+    if (o.digit_bits != 0 && o.digit_bits != 7 && o.digit_bits != 8)
+        return fail(FF_EINVAL, "digit_bits must be 0, 7 or 8");
+    if (o.winograd_levels < -1 || o.winograd_levels > 3)
+        return fail(FF_EINVAL, "winograd_levels must be -1..3");
+    if (o.preadd_mode < 0 || o.preadd_mode > 2)
+        return fail(FF_EINVAL, "preadd_mode must be 0, 1 or 2");
+
+    const Range base{-(int64_t)(p / 2), (int64_t)((p - 1) / 2)};
+
+    // Winograd levels: requested or from the crossover order w.
+    int L = o.winograd_levels;
+    const int64_t dmin = std::min({m, n, k});
+    if (L < 0) {
+        L = 0;
+        const int64_t w = crossover_w();
+        for (int64_t x = dmin; x >= w && L < 3; x /= 2) ++L;
+    }
+    // Every leaf dimension must keep at least 16 entries.
+    while (L > 0 && (dmin >> L) < 16) --L;
+    P.levels = L;
+    P.me = m - (m % (int64_t(1) << L));
+    P.ne = n - (n % (int64_t(1) << L));
+    P.ke = k - (k % (int64_t(1) << L));
+
+    // Leaf operand range, unreduced (delayed) and reduced pre-additions.
+    Range wid_d, wid_r = base;
+    int64_t mp_d, mp_r = mag(base) * mag(base);
+    leaf_bounds(base, L, &wid_d, &mp_d);
+    const bool delayed_fits = wid_d.lo >= -I32MAX && wid_d.hi <= I32MAX;
+
+    // Path.
+    int path = o.path == FF_PATH_AUTO ? FF_PATH_INT8 : o.path;
+    P.path = path;
+    const int64_t carry = (int64_t)p + 2;
+
+    if (path == FF_PATH_FP64) {
+        int64_t kb_d = delayed_fits ? (TWO53 - carry) / mp_d : 0;
+        int64_t kb_r = (TWO53 - carry) / mp_r;
+        bool reduce = L > 0 && kb_r > kb_d && kb_d < (P.ke >> L);
+        if (o.preadd_mode == 1) reduce = false;
+        if (o.preadd_mode == 2) reduce = L > 0;
+        if (!reduce && !delayed_fits)
+            return fail(FF_EUNSUPPORTED, "delayed pre-additions overflow 32 bits for this p");
+        int64_t kb = reduce ? kb_r : kb_d;
+        if (kb < 4)
+            return fail(FF_EUNSUPPORTED,
+                        "FP64 path: fewer than 4 products fit below 2^53 for this p");
+        P.preadds_reduced = reduce;
+        P.lo = reduce ? wid_r.lo : wid_d.lo;
+        P.hi = reduce ? wid_r.hi : wid_d.hi;
+        P.max_prod = reduce ? mp_r : mp_d;
+        P.kblock = kb;
+    } else {
+        int best_s = 0, best_bits = 0, best_reduce = 0;
+        for (int reduce = 0; reduce <= (L > 0 ? 1 : 0); ++reduce) {
+            if (!reduce && !delayed_fits) continue;
+            if (o.preadd_mode == 1 && reduce) continue;
+            if (o.preadd_mode == 2 && !reduce && L > 0) continue;
+            Range r = reduce ? wid_r : wid_d;
+            for (int bits : {7, 8}) {
+                if (o.digit_bits && bits != o.digit_bits) continue;
+                int s = slices_for(r, bits);
+                if (s == 0) continue;
+                // fewer slices wins; ties keep the delayed (unreduced) form and
+                // 7-bit digits
+                if (best_s == 0 || s < best_s) {
+                    best_s = s; best_bits = bits; best_reduce = reduce;
+                }
+            }
+        }
+        if (best_s == 0)
+            return fail(FF_EUNSUPPORTED, "INT8 path: operand range needs more than 5 digits");
+        Range r = best_reduce ? wid_r : wid_d;
+        P.preadds_reduced = best_reduce;
+        P.bits = best_bits;
+        P.slices = best_s;
+        P.lo = r.lo;
+        P.hi = r.hi;
+        P.max_prod = best_reduce ? mp_r : mp_d;
+        const int64_t d = digit_mag(r, best_bits, best_s);
+        P.kblock = I32MAX / ((int64_t)best_s * d * d);
+        P.tile = best_s;
+    }
+
+    // Workspace.
+    const int64_t ml = P.me >> L, nl = P.ne >> L, kl = P.ke >> L;
+    const int64_t nleaf = ipow7(L);
+    int64_t ws = 0;
+    if (P.path == FF_PATH_INT8) {
+        I8Tile t = i8_tile_for(P.slices);
+        const int64_t kpass = std::min<int64_t>(kl, P.kblock);
+        const int64_t KP = round_up(std::max<int64_t>(kpass, 1), I8_BK);
+        const int64_t mp = round_up(std::max<int64_t>(ml, 1), t.bm());
+        const int64_t np = round_up(std::max<int64_t>(nl, 1), t.bn());
+        ws += nleaf * P.slices * (mp + np) * KP;
+        if (L > 0) ws += nleaf * ml * nl * 4 + 256;
+    } else if (L > 0) {
+        ws += nleaf * (ml * kl + kl * nl) * 4 + nleaf * ml * nl * 4 + 256;
+    }
+    if (L > 0) ws += nleaf * 256 + 4096; // job tables
+    P.ws_bytes = ws;
+    *pl = P;
+    return FF_OK;
+}
+
+} // namespace ff

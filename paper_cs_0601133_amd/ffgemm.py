@@ -1,0 +1,284 @@
+"""Python binding of libffgemm.so: the C ABI of include/ffgemm.h, same names.
+
+Argument marshalling only.  Every step of the computation runs in the HIP
+library; if the library is missing this module raises at import-time use
+(there is no fallback).  Matrices may be given as torch tensors (int32 or
+uint32 storage of residues, row-major with unit column stride, on a ROCm
+device) or as raw device addresses (ints).
+"""
+import ctypes
+import os
+
+from . import build as _build
+
+FF_OK = 0
+FF_EINVAL = -1
+FF_EUNSUPPORTED = -2
+FF_ENOMEM = -3
+FF_EHIP = -4
+FF_EBUSY = -5
+FF_ENOTFOUND = -6
+
+FF_NOTRANS = 0
+FF_TRANS = 1
+
+FF_PATH_AUTO = 0
+FF_PATH_FP64 = 1
+FF_PATH_INT8 = 2
+
+_I64 = ctypes.c_int64
+_U32 = ctypes.c_uint32
+_INT = ctypes.c_int
+_VP = ctypes.c_void_p
+
+
+class ff_opts(ctypes.Structure):
+    _fields_ = [("path", _INT), ("winograd_levels", _INT), ("digit_bits", _INT),
+                ("validate", _INT), ("preadd_mode", _INT), ("stream", _VP)]
+
+
+class ff_plan_info(ctypes.Structure):
+    _fields_ = [("path", _INT), ("winograd_levels", _INT), ("preadds_reduced", _INT),
+                ("digit_bits", _INT), ("slices", _INT), ("operand_lo", _I64),
+                ("operand_hi", _I64), ("max_abs_product", _I64), ("kblock", _I64),
+                ("workspace_bytes", _I64), ("tile_config", _INT)]
+
+
+class ff_job(ctypes.Structure):
+    _fields_ = [("p", _U32), ("transA", _INT), ("transB", _INT), ("m", _I64), ("n", _I64),
+                ("k", _I64), ("alpha", _U32), ("beta", _U32), ("A", _VP), ("lda", _I64),
+                ("B", _VP), ("ldb", _I64), ("C", _VP), ("ldc", _I64)]
+
+
+# name -> (argtypes, restype)
+_SIGS = {
+    "ff_init": ([], _INT),
+    "ff_finalize": ([], _INT),
+    "ff_set_stream": ([_VP], _INT),
+    "ff_fgemm": ([_U32, _INT, _INT, _I64, _I64, _I64, _U32, _VP, _I64, _VP, _I64, _U32,
+                  _VP, _I64], _INT),
+    "ff_fgemm_ex": ([_U32, _INT, _INT, _I64, _I64, _I64, _U32, _VP, _I64, _VP, _I64, _U32,
+                     _VP, _I64, ctypes.POINTER(ff_opts)], _INT),
+    "ff_plan_query": ([_U32, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ff_opts),
+                       ctypes.POINTER(ff_plan_info)], _INT),
+    "ff_fgemm_batched": ([ctypes.POINTER(ff_job), _INT, ctypes.POINTER(ff_opts)], _INT),
+    "ff_batch_graph_create": ([ctypes.POINTER(ff_job), _INT, ctypes.POINTER(ff_opts),
+                               ctypes.POINTER(_VP)], _INT),
+    "ff_batch_graph_launch": ([_VP, _VP], _INT),
+    "ff_batch_graph_destroy": ([_VP], _INT),
+    "ff_server_create": ([_I64, ctypes.POINTER(ff_opts), ctypes.POINTER(_VP)], _INT),
+    "ff_server_submit": ([_VP, ctypes.POINTER(ff_job), ctypes.POINTER(ctypes.c_uint64)],
+                         _INT),
+    "ff_server_poll": ([_VP, ctypes.c_uint64, ctypes.POINTER(_INT)], _INT),
+    "ff_server_wait": ([_VP, ctypes.c_uint64], _INT),
+    "ff_server_stats": ([_VP, ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(_I64), ctypes.POINTER(_I64)], _INT),
+    "ff_server_destroy": ([_VP], _INT),
+    "ff_profile_enable": ([_INT], _INT),
+    "ff_profile_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)], _INT),
+    "ff_last_error": ([], ctypes.c_char_p),
+}
+
+EXPORTED = sorted(_SIGS)
+
+_lib = None
+
+
+def library_path():
+    return _build.LIB
+
+
+def load():
+    """Load libffgemm.so (it must have been built: see build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: the HIP library has not been built "
+                           "(python -m paper_cs_0601133_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+class FFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def _check(rc):
+    if rc != FF_OK:
+        raise FFError(rc, load().ff_last_error().decode())
+    return rc
+
+
+def _addr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _ld(x, default):
+    if x is None or isinstance(x, int):
+        return default
+    if x.dim() != 2:
+        raise ValueError("matrices must be 2-D")
+    if x.shape[1] > 1 and x.stride(1) != 1:
+        raise ValueError("matrices must have unit column stride (row-major)")
+    return max(x.stride(0), x.shape[1], 1)
+
+
+def make_opts(path=FF_PATH_AUTO, winograd_levels=-1, digit_bits=0, validate=0,
+              preadd_mode=0, stream=None):
+    return ff_opts(path, winograd_levels, digit_bits, validate, preadd_mode, stream)
+
+
+def _torch_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# --- the C ABI, same names --------------------------------------------------
+
+def ff_init():
+    return _check(load().ff_init())
+
+
+def ff_finalize():
+    return _check(load().ff_finalize())
+
+
+def ff_set_stream(stream):
+    return _check(load().ff_set_stream(stream))
+
+
+def ff_last_error():
+    return load().ff_last_error().decode()
+
+
+def ff_fgemm(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc):
+    return load().ff_fgemm(p, transA, transB, m, n, k, alpha, _addr(A), lda, _addr(B), ldb,
+                           beta, _addr(C), ldc)
+
+
+def ff_fgemm_ex(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_fgemm_ex(p, transA, transB, m, n, k, alpha, _addr(A), lda, _addr(B),
+                              ldb, beta, _addr(C), ldc, o)
+
+
+def ff_plan_query(p, transA, transB, m, n, k, opts=None):
+    info = ff_plan_info()
+    o = ctypes.byref(opts) if opts is not None else None
+    _check(load().ff_plan_query(p, transA, transB, m, n, k, o, ctypes.byref(info)))
+    return info
+
+
+def _jobs(jobs):
+    arr = (ff_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = j
+    return arr
+
+
+def ff_fgemm_batched(jobs, opts=None):
+    arr = _jobs(jobs)
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_fgemm_batched(arr, len(jobs), o)
+
+
+def ff_batch_graph_create(jobs, opts=None):
+    arr = _jobs(jobs)
+    o = ctypes.byref(opts) if opts is not None else None
+    g = _VP()
+    _check(load().ff_batch_graph_create(arr, len(jobs), o, ctypes.byref(g)))
+    return g.value
+
+
+def ff_batch_graph_launch(graph, stream=None):
+    return _check(load().ff_batch_graph_launch(graph, stream))
+
+
+def ff_batch_graph_destroy(graph):
+    return _check(load().ff_batch_graph_destroy(graph))
+
+
+def ff_server_create(hbm_budget_bytes, opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    s = _VP()
+    _check(load().ff_server_create(hbm_budget_bytes, o, ctypes.byref(s)))
+    return s.value
+
+
+def ff_server_submit(server, job):
+    rid = ctypes.c_uint64()
+    _check(load().ff_server_submit(server, ctypes.byref(job), ctypes.byref(rid)))
+    return rid.value
+
+
+def ff_server_poll(server, rid):
+    done = _INT()
+    _check(load().ff_server_poll(server, rid, ctypes.byref(done)))
+    return bool(done.value)
+
+
+def ff_server_wait(server, rid):
+    return _check(load().ff_server_wait(server, rid))
+
+
+def ff_server_stats(server):
+    p50, p99, gops = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    done, mx = _I64(), _I64()
+    _check(load().ff_server_stats(server, ctypes.byref(p50), ctypes.byref(p99),
+                                  ctypes.byref(gops), ctypes.byref(done), ctypes.byref(mx)))
+    return {"p50_ms": p50.value, "p99_ms": p99.value, "gops": gops.value,
+            "completed": done.value, "max_inflight": mx.value}
+
+
+def ff_profile_enable(on):
+    return _check(load().ff_profile_enable(int(bool(on))))
+
+
+def ff_profile_read():
+    g, s = ctypes.c_double(), ctypes.c_double()
+    ng, ns = _I64(), _I64()
+    _check(load().ff_profile_read(ctypes.byref(g), ctypes.byref(ng), ctypes.byref(s),
+                                  ctypes.byref(ns)))
+    return {"gemm_ms": g.value, "gemm_launches": ng.value, "slice_ms": s.value,
+            "slice_launches": ns.value}
+
+
+def ff_server_destroy(server):
+    return _check(load().ff_server_destroy(server))
+
+
+# --- marshalling helpers for torch tensors ----------------------------------
+
+def job(p, A, B, C, alpha=1, beta=0, transA=False, transB=False):
+    """An ff_job for torch tensors A, B, C (op(A) is m x k, op(B) k x n)."""
+    m = A.shape[1] if transA else A.shape[0]
+    k = A.shape[0] if transA else A.shape[1]
+    n = B.shape[0] if transB else B.shape[1]
+    return ff_job(p, int(transA), int(transB), m, n, k, alpha % p, beta % p, _addr(A),
+                  _ld(A, 1), _addr(B), _ld(B, 1), _addr(C), _ld(C, 1))
+
+
+def fgemm(p, A, B, C, alpha=1, beta=0, transA=False, transB=False, opts=None):
+    """C <- (alpha*op(A)*op(B) + beta*C) mod p on torch's current stream."""
+    j = job(p, A, B, C, alpha, beta, transA, transB)
+    if opts is None:
+        opts = make_opts()
+    if not opts.stream:
+        opts.stream = _torch_stream()
+    return _check(ff_fgemm_ex(j.p, j.transA, j.transB, j.m, j.n, j.k, j.alpha, j.A, j.lda,
+                              j.B, j.ldb, j.beta, j.C, j.ldc, opts))

@@ -1,0 +1,147 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute calls).
+
+* libffgemm.so loads and exports every function include/ffgemm.h declares;
+* the planner (ff_plan_query, C++) agrees with the oracle's bound
+  calculator (Python, exact integers) on K-blocks, slice counts, operand
+  ranges and leaf product bounds;
+* argument errors come back as status codes with a message, before any
+  device is touched.
+"""
+import os
+import re
+
+import pytest
+
+from oracle import bounds as bd
+from paper_cs_0601133_amd import ffgemm as ff
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ffgemm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ff_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ff.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == ff.EXPORTED
+
+
+P_LIST = [2, 3, 5, 251, 65521, 1048573, 8388593, 2147483647]
+
+
+@pytest.mark.parametrize("p", P_LIST)
+def test_plan_fp64_kblock_matches_bound(p):
+    o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0)
+    lo, hi = bd.centered_range(p)
+    M = max(-lo, hi)
+    kb = bd.fp64_kblock(M * M, p + 2)
+    if kb < 4:
+        with pytest.raises(ff.FFError) as e:
+            ff.ff_plan_query(p, 0, 0, 64, 64, 64, o)
+        assert e.value.status == ff.FF_EUNSUPPORTED
+        return
+    info = ff.ff_plan_query(p, 0, 0, 64, 64, 64, o)
+    assert info.path == ff.FF_PATH_FP64
+    assert info.kblock == kb
+    assert (info.operand_lo, info.operand_hi) == (lo, hi)
+    assert info.max_abs_product == M * M
+
+
+@pytest.mark.parametrize("p", P_LIST)
+@pytest.mark.parametrize("bits", [7, 8])
+def test_plan_int8_slices_match_bound(p, bits):
+    o = ff.make_opts(path=ff.FF_PATH_INT8, winograd_levels=0, digit_bits=bits)
+    lo, hi = bd.centered_range(p)
+    s = bd.slices_needed(lo, hi, bits)
+    if s > 5:
+        with pytest.raises(ff.FFError):
+            ff.ff_plan_query(p, 0, 0, 64, 64, 64, o)
+        return
+    info = ff.ff_plan_query(p, 0, 0, 64, 64, 64, o)
+    assert info.slices == s
+    d = bd.digit_max_abs(lo, hi, bits, s)
+    assert info.kblock == bd.int32_kblock(d, d, s)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+@pytest.mark.parametrize("p", [251, 65521, 8388593])
+def test_plan_winograd_leaf_bounds(L, p):
+    lo, hi = bd.centered_range(p)
+    wl, wh = bd.winograd_leaf_operand_range(lo, hi, lo, hi, L)
+    mp = bd.winograd_leaf_max_product(lo, hi, lo, hi, L)
+    # delayed (unreduced) pre-additions, FP64 path
+    o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=L, preadd_mode=1)
+    kb = bd.fp64_kblock(mp, p + 2)
+    if kb >= 4:
+        info = ff.ff_plan_query(p, 0, 0, 1024, 1024, 1024, o)
+        assert info.winograd_levels == L and info.preadds_reduced == 0
+        assert (info.operand_lo, info.operand_hi) == (wl, wh)
+        assert info.max_abs_product == mp
+        assert info.kblock == kb
+    # delayed pre-additions, INT8 path, 7-bit digits
+    o = ff.make_opts(path=ff.FF_PATH_INT8, winograd_levels=L, preadd_mode=1, digit_bits=7)
+    info = ff.ff_plan_query(p, 0, 0, 1024, 1024, 1024, o)
+    assert info.slices == bd.slices_needed(wl, wh, 7)
+    # reduced pre-additions: leaves are centered residues again
+    o = ff.make_opts(path=ff.FF_PATH_INT8, winograd_levels=L, preadd_mode=2, digit_bits=8)
+    info = ff.ff_plan_query(p, 0, 0, 1024, 1024, 1024, o)
+    assert info.preadds_reduced == 1
+    assert info.slices == bd.slices_needed(lo, hi, 8)
+
+
+def test_plan_configs_of_the_workloads():
+    # n = 4096, p = 8388593: FP64 K-block 512; INT8 with 4 signed 7-bit digits
+    i = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096,
+                         ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0))
+    assert i.kblock == 512
+    i = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096,
+                         ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7, winograd_levels=0))
+    assert i.slices == 4 and i.kblock >= 4096
+    # p = 251: one direct int8 plane, exact int32 sums up to k = 137438
+    i = ff.ff_plan_query(251, 0, 0, 8192, 8192, 8192,
+                         ff.make_opts(path=ff.FF_PATH_INT8, winograd_levels=0))
+    assert i.slices == 1 and i.kblock == 137438
+    # Winograd leaves at p = 8388593: FP64 K-blocks 56 (l = 1) and 6 (l = 2)
+    for L, kb in ((1, 56), (2, 6)):
+        i = ff.ff_plan_query(8388593, 0, 0, 8192, 8192, 8192,
+                             ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=L,
+                                          preadd_mode=1))
+        assert i.kblock == kb
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((1, 0, 0, 4, 4, 4, 1, 8, 4, 8, 4, 0, 8, 4), "p must"),
+    ((7, 2, 0, 4, 4, 4, 1, 8, 4, 8, 4, 0, 8, 4), "trans"),
+    ((7, 0, 0, -1, 4, 4, 1, 8, 4, 8, 4, 0, 8, 4), "negative"),
+    ((7, 0, 0, 4, 4, 4, 1, 8, 3, 8, 4, 0, 8, 4), "lda"),
+    ((7, 0, 0, 4, 4, 4, 1, 8, 4, 8, 3, 0, 8, 4), "ldb"),
+    ((7, 0, 0, 4, 4, 4, 1, 8, 4, 8, 4, 0, 8, 3), "ldc"),
+    ((7, 0, 0, 4, 4, 4, 1, None, 4, 8, 4, 0, 8, 4), "null"),
+    ((7, 0, 0, 4, 4, 4, 1, 8, 4, 8, 4, 0, None, 4), "null"),
+    ((7, 1, 0, 4, 5, 3, 1, 8, 3, 8, 5, 0, 8, 5), "lda"),
+])
+def test_argument_errors(args, msg):
+    rc = ff.ff_fgemm(*args)
+    assert rc == ff.FF_EINVAL
+    assert msg in ff.ff_last_error()
+
+
+def test_empty_product_is_a_no_op_without_device():
+    # m == 0 or n == 0 returns before any device call
+    assert ff.ff_fgemm(7, 0, 0, 0, 4, 4, 1, None, 4, None, 4, 0, None, 4) == ff.FF_OK
+    assert ff.ff_fgemm(7, 0, 0, 4, 0, 4, 1, None, 4, None, 4, 0, None, 4) == ff.FF_OK
+
+
+def test_bad_options():
+    for o in (ff.make_opts(path=5), ff.make_opts(digit_bits=6),
+              ff.make_opts(winograd_levels=4), ff.make_opts(preadd_mode=3)):
+        with pytest.raises(ff.FFError) as e:
+            ff.ff_plan_query(7, 0, 0, 8, 8, 8, o)
+        assert e.value.status == ff.FF_EINVAL
