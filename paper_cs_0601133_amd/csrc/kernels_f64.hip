@@ -158,15 +158,15 @@ __device__ void f64_tile(const F64Job &J, int tm, int tn, double *smem)
         __syncthreads();
     }
 
-    // Epilogue: lane holds rows 4*(lane/16) + r, column lane%16 of each
-    // 16 x 16 block.
+    // Epilogue: in each 16 x 16 block the lane holds column lane%16 of rows
+    // lane/16 + 4r, r = 0..3 (v_mfma_f64_16x16x4 result layout).
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+                const int row = m0 + wm0 + i * 16 + (lane >> 4) + 4 * r;
                 const int col = n0 + wn0 + j * 16 + (lane & 15);
                 if (row < J.m && col < J.n) {
                     const uint32_t v = canon_f64(acc[i][j][r], J.pd, J.pinv, J.p);
