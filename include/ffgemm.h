@@ -179,6 +179,16 @@ int ff_server_stats(void *server, double *p50_ms, double *p99_ms, double *gops,
                     int64_t *completed, int64_t *max_inflight);
 int ff_server_destroy(void *server);
 
+/* Autotuner (the self-adapting thresholds of Section 7 applied to kernel
+ * tiling).  Times every compiled INT8 tile configuration for the given
+ * number of digit slices on an m x n x k product, using scratch buffers of
+ * its own on the ff_set_stream stream, and records the fastest in the tuning
+ * cache (file FF_TUNE_CACHE, else $HOME/.cache/ffgemm/tune_gfx950.txt) that
+ * later plans of the same slice count and size class use.  Synchronous.
+ * *best_tile receives the configuration id, *best_ms its kernel time. */
+int ff_autotune(int slices, int64_t m, int64_t n, int64_t k, int *best_tile,
+                double *best_ms);
+
 /* Kernel timing for measurement.  While enabled, every launch of the
  * matrix-core kernels (FP64 and INT8 fgemm, single or batched) is bracketed
  * by a HIP event pair recorded on the stream it is launched on, and so is

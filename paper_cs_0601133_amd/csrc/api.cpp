@@ -220,7 +220,7 @@ int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
                  int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const Plan &P,
                  void *ws, hipStream_t st)
 {
-    const I8Tile t = i8_tile_for(P.slices);
+    const I8Tile &t = i8_tile(P.tile);
     const int64_t kpass = std::min<int64_t>(k, P.kblock);
     const int KP = (int)round_up(kpass, I8_BK);
     const int mp = (int)round_up(m, t.bm()), np = (int)round_up(n, t.bn());
@@ -247,7 +247,7 @@ int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
         J.pd = (double)p; J.pinv = 1.0 / (double)p;
         digit_weights(p, alpha, P.slices == 1 ? 8 : P.bits, P.slices, J.w);
         J.tiles_m = mp / t.bm(); J.tiles_n = np / t.bn();
-        FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_i8(P.slices, J, st)));
+        FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_i8(P.tile, J, st)));
     }
     return FF_OK;
 }

@@ -31,8 +31,11 @@ int fail(int status, const std::string &msg);
 constexpr int F64_BM = 128, F64_BN = 128, F64_BK = 16, F64_THREADS = 256;
 
 // INT8 kernel: workgroup tile BM x BN, K step 64 bytes, waves of 64 lanes
-// each owning (32*TM) x (32*TN) outputs.  One configuration per slice count.
+// each owning (32*TM) x (32*TN) outputs.  Several configurations per slice
+// count are compiled; the planner picks one (default table, autotuner cache
+// or an explicit id).
 struct I8Tile {
+    int id;
     int S;      // digits per operand (compile-time in the kernel)
     int TM, TN; // 32x32 MFMA tiles per wave
     int WGM, WGN;
@@ -40,7 +43,12 @@ struct I8Tile {
     int bn() const { return WGN * 32 * TN; }
     int threads() const { return 64 * WGM * WGN; }
 };
-I8Tile i8_tile_for(int S);
+// Registry of compiled configurations (kernels_i8.hip).
+int i8_tile_count();
+const I8Tile &i8_tile(int id);
+int i8_default_tile(int S);
+// Tile chosen by the autotuner for this slice count and size, or -1.
+int tuned_i8_tile(int S, int64_t m, int64_t n, int64_t k);
 constexpr int I8_BK = 64;
 
 // ---------------------------------------------------------------------------
@@ -131,15 +139,17 @@ hipError_t launch_f64(const F64Job &job, hipStream_t st);
 // Batched FP64: device job table; grid = total tiles (persistent == 0) or a
 // persistent grid draining a tile counter (ctr: 2 words, zero on entry, left
 // at zero on exit).
+// All jobs of one table share transposes (ta, tb) and input mode.
 hipError_t launch_f64_batched(const F64Job *dev_jobs, int njobs, int total_tiles,
-                              int persistent, unsigned *ctr, hipStream_t st);
+                              int persistent, unsigned *ctr, int ta, int tb, int mode,
+                              hipStream_t st);
 
 hipError_t launch_slice(const SliceJob &job, hipStream_t st);
 hipError_t launch_slice_batched(const SliceJob *dev_jobs, int njobs,
                                 int total_blocks, hipStream_t st);
 
-hipError_t launch_i8(int S, const I8Job &job, hipStream_t st);
-hipError_t launch_i8_batched(int S, const I8Job *dev_jobs, int njobs,
+hipError_t launch_i8(int tile, const I8Job &job, hipStream_t st);
+hipError_t launch_i8_batched(int tile, const I8Job *dev_jobs, int njobs,
                              int total_tiles, int persistent, unsigned *ctr,
                              hipStream_t st);
 

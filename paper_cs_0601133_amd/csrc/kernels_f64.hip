@@ -20,80 +20,104 @@ namespace {
 
 constexpr int LDP = F64_BM + 16; // padded LDS row, in doubles
 
+// One stage's operand words as loaded (raw) with in-matrix flags; they are
+// converted after the stage's MFMAs so that the loads' latency overlaps them.
 struct F64Regs {
-    int32_t a[8];
-    int32_t b[8];
+    uint32_t a[8];
+    uint32_t b[8];
+    uint32_t oka, okb; // bit q: element q lies inside the matrix
 };
 
-__device__ __forceinline__ int32_t fetch(const F64Job &J, const void *X,
-                                         int64_t off, bool ok, uint32_t half)
+// Operand element (clamped address, always in bounds) -> centered value, or
+// 0 outside the matrix.  The loads are unconditional so that all of a
+// stage's loads are in flight together.
+template <int MODE>
+__device__ __forceinline__ int32_t cvt(uint32_t raw, bool ok, uint32_t p, uint32_t half)
 {
-    if (!ok) return 0;
-    if (J.in_mode == IN_SIGNED) return ((const int32_t *)X)[off];
-    return center(((const uint32_t *)X)[off], J.p, half);
+    const int32_t v = MODE == IN_SIGNED ? (int32_t)raw : center(raw, p, half);
+    return ok ? v : 0;
 }
 
+template <int TA, int TB, int MODE>
 __device__ __forceinline__ void load_stage(const F64Job &J, int m0, int n0,
                                            int k0, int tid, uint32_t half,
                                            F64Regs &R)
 {
-    if (!J.transA) { // A is m x k: lanes run along k
-        const int kk = tid & 15, kg = k0 + kk;
+    const uint32_t *A = (const uint32_t *)J.A;
+    const uint32_t *B = (const uint32_t *)J.B;
+    const int km = J.k - 1, mm = J.m - 1, nm = J.n - 1;
+    uint32_t oka = 0, okb = 0;
+    if (!TA) { // A is m x k: lanes run along k
+        const int kg = k0 + (tid & 15);
+        const int kc = kg < km ? kg : km;
         const int r0 = m0 + (tid >> 4);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int r = r0 + 16 * q;
-            R.a[q] = fetch(J, J.A, (int64_t)r * J.lda + kg, r < J.m && kg < J.k, half);
+            R.a[q] = A[(int64_t)(r < mm ? r : mm) * J.lda + kc];
+            oka |= (uint32_t)(r < J.m && kg < J.k) << q;
         }
     } else { // A is k x m: lanes run along m
         const int r = m0 + (tid & 127), kq = k0 + (tid >> 7);
+        const int rc = r < mm ? r : mm;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int kg = kq + 2 * q;
-            R.a[q] = fetch(J, J.A, (int64_t)kg * J.lda + r, r < J.m && kg < J.k, half);
+            R.a[q] = A[(int64_t)(kg < km ? kg : km) * J.lda + rc];
+            oka |= (uint32_t)(r < J.m && kg < J.k) << q;
         }
     }
-    if (!J.transB) { // B is k x n: lanes run along n
+    if (!TB) { // B is k x n: lanes run along n
         const int c = n0 + (tid & 127), kq = k0 + (tid >> 7);
+        const int cc = c < nm ? c : nm;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int kg = kq + 2 * q;
-            R.b[q] = fetch(J, J.B, (int64_t)kg * J.ldb + c, c < J.n && kg < J.k, half);
+            R.b[q] = B[(int64_t)(kg < km ? kg : km) * J.ldb + cc];
+            okb |= (uint32_t)(c < J.n && kg < J.k) << q;
         }
     } else { // B is n x k: lanes run along k
-        const int kk = tid & 15, kg = k0 + kk;
+        const int kg = k0 + (tid & 15);
+        const int kc = kg < km ? kg : km;
         const int c0 = n0 + (tid >> 4);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int c = c0 + 16 * q;
-            R.b[q] = fetch(J, J.B, (int64_t)c * J.ldb + kg, c < J.n && kg < J.k, half);
+            R.b[q] = B[(int64_t)(c < nm ? c : nm) * J.ldb + kc];
+            okb |= (uint32_t)(c < J.n && kg < J.k) << q;
         }
     }
+    R.oka = oka;
+    R.okb = okb;
 }
 
-__device__ __forceinline__ void store_stage(const F64Job &J, int tid,
-                                            const F64Regs &R,
-                                            double (*sA)[LDP],
+template <int TA, int TB, int MODE>
+__device__ __forceinline__ void store_stage(int tid, const F64Regs &R, uint32_t p,
+                                            uint32_t half, double (*sA)[LDP],
                                             double (*sB)[LDP])
 {
-    if (!J.transA) {
+#define VA(q) (double)cvt<MODE>(R.a[q], (R.oka >> (q)) & 1u, p, half)
+#define VB(q) (double)cvt<MODE>(R.b[q], (R.okb >> (q)) & 1u, p, half)
+    if (!TA) {
         const int kk = tid & 15, r0 = tid >> 4;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sA[kk][r0 + 16 * q] = (double)R.a[q];
+        for (int q = 0; q < 8; ++q) sA[kk][r0 + 16 * q] = VA(q);
     } else {
         const int r = tid & 127, kq = tid >> 7;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sA[kq + 2 * q][r] = (double)R.a[q];
+        for (int q = 0; q < 8; ++q) sA[kq + 2 * q][r] = VA(q);
     }
-    if (!J.transB) {
+    if (!TB) {
         const int c = tid & 127, kq = tid >> 7;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sB[kq + 2 * q][c] = (double)R.b[q];
+        for (int q = 0; q < 8; ++q) sB[kq + 2 * q][c] = VB(q);
     } else {
         const int kk = tid & 15, c0 = tid >> 4;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sB[kk][c0 + 16 * q] = (double)R.b[q];
+        for (int q = 0; q < 8; ++q) sB[kk][c0 + 16 * q] = VB(q);
     }
+#undef VA
+#undef VB
 }
 
 __device__ __forceinline__ void fold(v4d (&acc)[4][4], double pd, double pinv)
@@ -110,6 +134,7 @@ __device__ __forceinline__ void fold(v4d (&acc)[4][4], double pd, double pinv)
 }
 
 // One 128 x 128 output tile.  smem: 2 stages x (A, B) x 16 x LDP doubles.
+template <int TA, int TB, int MODE>
 __device__ void f64_tile(const F64Job &J, int tm, int tn, double *smem)
 {
     const int tid = threadIdx.x;
@@ -128,14 +153,14 @@ __device__ void f64_tile(const F64Job &J, int tm, int tn, double *smem)
 
     const int nk = (J.k + F64_BK - 1) / F64_BK;
     F64Regs R;
-    load_stage(J, m0, n0, 0, tid, half, R);
-    store_stage(J, tid, R, sA[0], sB[0]);
+    load_stage<TA, TB, MODE>(J, m0, n0, 0, tid, half, R);
+    store_stage<TA, TB, MODE>(tid, R, J.p, half, sA[0], sB[0]);
     __syncthreads();
 
     int cnt = 0;
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) load_stage(J, m0, n0, (kt + 1) * F64_BK, tid, half, R);
+        if (kt + 1 < nk) load_stage<TA, TB, MODE>(J, m0, n0, (kt + 1) * F64_BK, tid, half, R);
 #pragma unroll
         for (int ks = 0; ks < F64_BK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
@@ -154,7 +179,7 @@ __device__ void f64_tile(const F64Job &J, int tm, int tn, double *smem)
                 cnt = 0;
             }
         }
-        if (kt + 1 < nk) store_stage(J, tid, R, sA[buf ^ 1], sB[buf ^ 1]);
+        if (kt + 1 < nk) store_stage<TA, TB, MODE>(tid, R, J.p, half, sA[buf ^ 1], sB[buf ^ 1]);
         __syncthreads();
     }
 
@@ -180,6 +205,7 @@ __device__ void f64_tile(const F64Job &J, int tm, int tn, double *smem)
 
 constexpr size_t F64_SMEM = sizeof(double) * 2 * 2 * F64_BK * LDP;
 
+template <int TA, int TB, int MODE>
 __global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64(F64Job J)
 {
     __shared__ double smem[F64_SMEM / sizeof(double)];
@@ -187,7 +213,24 @@ __global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64(F64Job J)
     const int t = xcd_remap(blockIdx.x, G);
     int tm, tn;
     grouped_tile<8>(t, J.tiles_m, J.tiles_n, &tm, &tn);
-    f64_tile(J, tm, tn, smem);
+    f64_tile<TA, TB, MODE>(J, tm, tn, smem);
+}
+
+// Runtime flags -> instantiation.
+template <template <int, int, int> class K, class... Args>
+hipError_t f64_dispatch(int ta, int tb, int mode, Args... args)
+{
+    const int key = ta * 4 + tb * 2 + mode;
+    switch (key) {
+    case 0: return K<0, 0, 0>::go(args...);
+    case 1: return K<0, 0, 1>::go(args...);
+    case 2: return K<0, 1, 0>::go(args...);
+    case 3: return K<0, 1, 1>::go(args...);
+    case 4: return K<1, 0, 0>::go(args...);
+    case 5: return K<1, 0, 1>::go(args...);
+    case 6: return K<1, 1, 0>::go(args...);
+    default: return K<1, 1, 1>::go(args...);
+    }
 }
 
 __device__ __forceinline__ int find_job_f64(const F64Job *jobs, int njobs, int g)
@@ -200,6 +243,7 @@ __device__ __forceinline__ int find_job_f64(const F64Job *jobs, int njobs, int g
     return lo;
 }
 
+template <int TA, int TB, int MODE>
 __global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64_batched(
     const F64Job *__restrict__ jobs, int njobs, int total, int persistent,
     unsigned *ctr)
@@ -220,7 +264,7 @@ __global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64_batched(
         const int local = g - J.tile_start;
         int tm, tn;
         grouped_tile<8>(local, J.tiles_m, J.tiles_n, &tm, &tn);
-        f64_tile(J, tm, tn, smem);
+        f64_tile<TA, TB, MODE>(J, tm, tn, smem);
         if (!persistent) break;
     }
     if (persistent && threadIdx.x == 0) {
@@ -235,17 +279,38 @@ __global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64_batched(
     }
 }
 
+template <int TA, int TB, int MODE>
+struct SingleF64 {
+    static hipError_t go(const F64Job &job, hipStream_t st)
+    {
+        const int G = job.tiles_m * job.tiles_n;
+        hipLaunchKernelGGL((k_fgemm_f64<TA, TB, MODE>), dim3(G), dim3(F64_THREADS), 0, st, job);
+        return hipGetLastError();
+    }
+};
+
+template <int TA, int TB, int MODE>
+struct BatchedF64 {
+    static hipError_t go(const F64Job *jobs, int njobs, int total, int persistent,
+                         unsigned *ctr, int grid, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_fgemm_f64_batched<TA, TB, MODE>), dim3(grid), dim3(F64_THREADS),
+                           0, st, jobs, njobs, total, persistent, ctr);
+        return hipGetLastError();
+    }
+};
+
 } // namespace
 
 hipError_t launch_f64(const F64Job &job, hipStream_t st)
 {
-    const int G = job.tiles_m * job.tiles_n;
-    hipLaunchKernelGGL(k_fgemm_f64, dim3(G), dim3(F64_THREADS), 0, st, job);
-    return hipGetLastError();
+    return f64_dispatch<SingleF64>(job.transA, job.transB, job.in_mode, job, st);
 }
 
+// A batched table must share transposes and input mode (the first job's).
 hipError_t launch_f64_batched(const F64Job *dev_jobs, int njobs, int total_tiles,
-                              int persistent, unsigned *ctr, hipStream_t st)
+                              int persistent, unsigned *ctr, int ta, int tb, int mode,
+                              hipStream_t st)
 {
     int grid = total_tiles;
     if (persistent) {
@@ -255,9 +320,8 @@ hipError_t launch_f64_batched(const F64Job *dev_jobs, int njobs, int total_tiles
         grid = cus * 2 < total_tiles ? cus * 2 : total_tiles;
         if (grid < 1) grid = 1;
     }
-    hipLaunchKernelGGL(k_fgemm_f64_batched, dim3(grid), dim3(F64_THREADS), 0, st,
-                       dev_jobs, njobs, total_tiles, persistent, ctr);
-    return hipGetLastError();
+    return f64_dispatch<BatchedF64>(ta, tb, mode, (const F64Job *)dev_jobs, njobs, total_tiles,
+                                    persistent, ctr, grid, st);
 }
 
 } // namespace ff

@@ -240,9 +240,15 @@ __device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
             }
 }
 
+// Waves per SIMD implied by the workgroup size (one workgroup per CU).
+template <int WGM, int WGN>
+struct Wpe {
+    static constexpr int v = (WGM * WGN) / 4 > 0 ? (WGM * WGN) / 4 : 1;
+};
+
 template <int S, int TM, int TN, int WGM, int WGN>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
-                          amdgpu_waves_per_eu(1, 1)))
+                          amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
 void k_fgemm_i8(I8Job J)
 {
     using C = Cfg<S, TM, TN, WGM, WGN>;
@@ -256,7 +262,7 @@ void k_fgemm_i8(I8Job J)
 
 template <int S, int TM, int TN, int WGM, int WGN>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
-                          amdgpu_waves_per_eu(1, 1)))
+                          amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
 void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
                         int persistent, unsigned *ctr)
 {
@@ -321,28 +327,57 @@ hipError_t run_batched(const I8Job *jobs, int njobs, int total, int persistent,
 
 } // namespace
 
-// The instantiations below must match i8_tile_for() in plan.cpp.
-hipError_t launch_i8(int S, const I8Job &J, hipStream_t st)
+// Compiled configurations: id, S, TM, TN, WGM, WGN.  Each (WGM x WGN)
+// workgroup of 64-lane waves owns a (WGM*32*TM) x (WGN*32*TN) tile of C;
+// 2S-1 accumulator sets of TM*TN 32x32 blocks live in each wave.
+#define FF_I8_TILES(X)                                                            \
+    X(0, 1, 2, 2, 2, 2)  /* 128 x 128, 4 waves,   64 acc */                        \
+    X(1, 1, 2, 2, 4, 2)  /* 256 x 128, 8 waves,   64 acc */                        \
+    X(2, 1, 2, 4, 2, 2)  /* 128 x 256, 4 waves,  128 acc */                        \
+    X(3, 2, 2, 2, 2, 2)  /* 128 x 128, 4 waves,  192 acc */                        \
+    X(4, 2, 1, 2, 4, 2)  /* 128 x 128, 8 waves,   96 acc */                        \
+    X(5, 3, 1, 2, 4, 1)  /* 128 x  64, 4 waves,  160 acc */                        \
+    X(6, 3, 1, 2, 4, 2)  /* 128 x 128, 8 waves,  160 acc */                        \
+    X(7, 3, 1, 1, 4, 2)  /* 128 x  64, 8 waves,   80 acc */                        \
+    X(8, 4, 1, 1, 4, 2)  /* 128 x  64, 8 waves,  112 acc */                        \
+    X(9, 4, 1, 1, 2, 2)  /*  64 x  64, 4 waves,  112 acc */                        \
+    X(10, 4, 1, 1, 2, 4) /*  64 x 128, 8 waves,  112 acc */                        \
+    X(11, 5, 1, 1, 4, 1) /* 128 x  32, 4 waves,  144 acc */                        \
+    X(12, 5, 1, 1, 4, 2) /* 128 x  64, 8 waves,  144 acc */
+
+namespace {
+const I8Tile k_tiles[] = {
+#define FF_ROW(id, S, TM, TN, WGM, WGN) I8Tile{id, S, TM, TN, WGM, WGN},
+    FF_I8_TILES(FF_ROW)
+#undef FF_ROW
+};
+// Default configuration per slice count (index = S).
+const int k_default[6] = {-1, 0, 4, 6, 8, 12};
+} // namespace
+
+int i8_tile_count() { return (int)(sizeof(k_tiles) / sizeof(k_tiles[0])); }
+const I8Tile &i8_tile(int id) { return k_tiles[id]; }
+int i8_default_tile(int S) { return (S >= 1 && S <= 5) ? k_default[S] : -1; }
+
+hipError_t launch_i8(int tile, const I8Job &J, hipStream_t st)
 {
-    switch (S) {
-    case 1: return run_single<1, 2, 2, 2, 2>(J, st);
-    case 2: return run_single<2, 2, 2, 2, 2>(J, st);
-    case 3: return run_single<3, 1, 2, 4, 1>(J, st);
-    case 4: return run_single<4, 1, 2, 4, 1>(J, st);
-    case 5: return run_single<5, 1, 1, 4, 1>(J, st);
+    switch (tile) {
+#define FF_CASE(id, S, TM, TN, WGM, WGN)                                            \
+    case id: return run_single<S, TM, TN, WGM, WGN>(J, st);
+        FF_I8_TILES(FF_CASE)
+#undef FF_CASE
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_i8_batched(int S, const I8Job *jobs, int njobs, int total,
+hipError_t launch_i8_batched(int tile, const I8Job *jobs, int njobs, int total,
                              int persistent, unsigned *ctr, hipStream_t st)
 {
-    switch (S) {
-    case 1: return run_batched<1, 2, 2, 2, 2>(jobs, njobs, total, persistent, ctr, st);
-    case 2: return run_batched<2, 2, 2, 2, 2>(jobs, njobs, total, persistent, ctr, st);
-    case 3: return run_batched<3, 1, 2, 4, 1>(jobs, njobs, total, persistent, ctr, st);
-    case 4: return run_batched<4, 1, 2, 4, 1>(jobs, njobs, total, persistent, ctr, st);
-    case 5: return run_batched<5, 1, 1, 4, 1>(jobs, njobs, total, persistent, ctr, st);
+    switch (tile) {
+#define FF_CASE(id, S, TM, TN, WGM, WGN)                                            \
+    case id: return run_batched<S, TM, TN, WGM, WGN>(jobs, njobs, total, persistent, ctr, st);
+        FF_I8_TILES(FF_CASE)
+#undef FF_CASE
     default: return hipErrorInvalidValue;
     }
 }

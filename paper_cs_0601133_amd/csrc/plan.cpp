@@ -24,17 +24,6 @@
 
 namespace ff {
 
-I8Tile i8_tile_for(int S)
-{
-    switch (S) {
-    case 1: return I8Tile{1, 2, 2, 2, 2}; // 128 x 128, 1 accumulator set
-    case 2: return I8Tile{2, 2, 2, 2, 2}; // 128 x 128, 3 sets
-    case 3: return I8Tile{3, 1, 2, 4, 1}; // 128 x 64, 5 sets
-    case 4: return I8Tile{4, 1, 2, 4, 1}; // 128 x 64, 7 sets
-    default: return I8Tile{5, 1, 1, 4, 1}; // 128 x 32, 9 sets
-    }
-}
-
 namespace {
 
 constexpr int64_t TWO53 = int64_t(1) << 53;
@@ -122,6 +111,20 @@ int64_t digit_mag(Range r, int bits, int S)
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 int64_t ipow7(int L) { int64_t r = 1; while (L--) r *= 7; return r; }
+
+// Tile configuration for the INT8 kernel: FF_I8_TILE (an id of the right
+// slice count) overrides; else the autotuner's cache; else the default.
+int choose_i8_tile(int S, int64_t m, int64_t n, int64_t k, const ff_opts &)
+{
+    const char *e = std::getenv("FF_I8_TILE");
+    if (e && *e) {
+        const int id = std::atoi(e);
+        if (id >= 0 && id < i8_tile_count() && i8_tile(id).S == S) return id;
+    }
+    const int tuned = tuned_i8_tile(S, m, n, k);
+    if (tuned >= 0) return tuned;
+    return i8_default_tile(S);
+}
 
 int crossover_w()
 {
@@ -221,7 +224,7 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         P.max_prod = best_reduce ? mp_r : mp_d;
         const int64_t d = digit_mag(r, best_bits, best_s);
         P.kblock = I32MAX / ((int64_t)best_s * d * d);
-        P.tile = best_s;
+        P.tile = choose_i8_tile(best_s, P.me >> L, P.ne >> L, P.ke >> L, o);
     }
 
     // Workspace.
@@ -229,7 +232,7 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
     const int64_t nleaf = ipow7(L);
     int64_t ws = 0;
     if (P.path == FF_PATH_INT8) {
-        I8Tile t = i8_tile_for(P.slices);
+        const I8Tile &t = i8_tile(P.tile);
         const int64_t kpass = std::min<int64_t>(kl, P.kblock);
         const int64_t KP = round_up(std::max<int64_t>(kpass, 1), I8_BK);
         const int64_t mp = round_up(std::max<int64_t>(ml, 1), t.bm());

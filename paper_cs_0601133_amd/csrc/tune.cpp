@@ -1,0 +1,164 @@
+// Autotuner for the INT8 kernel's tile configuration.
+//
+// The paper leaves its thresholds to experiment (the Winograd crossover
+// order w, Section 3.2.1) and names self-adapting software as future work
+// (Section 7).  Here the tunable is the workgroup/wave tiling of the digit
+// GEMM: ff_autotune times every compiled configuration of a slice count on
+// a given problem size (on scratch buffers of its own) and records the
+// fastest in a text cache, one line per (slice count, size class):
+//     S  class  tile_id  best_ms
+// The size class is floor(log2(m*n*k)) / 3 (about one class per doubling of
+// the matrix order).  The cache path is FF_TUNE_CACHE, else
+// $HOME/.cache/ffgemm/tune_gfx950.txt; it is read once per process.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include <sys/stat.h>
+
+#include "ff_profile.h"
+#include "ff_runtime.h"
+
+namespace ff {
+
+namespace {
+std::mutex g_tmu;
+bool g_loaded = false;
+std::map<std::pair<int, int>, int> g_table;
+
+std::string cache_path()
+{
+    const char *e = std::getenv("FF_TUNE_CACHE");
+    if (e && *e) return e;
+    const char *h = std::getenv("HOME");
+    return std::string(h ? h : ".") + "/.cache/ffgemm/tune_gfx950.txt";
+}
+
+int size_class(int64_t m, int64_t n, int64_t k)
+{
+    const double v = (double)std::max<int64_t>(m, 1) * (double)std::max<int64_t>(n, 1) *
+                     (double)std::max<int64_t>(k, 1);
+    return (int)std::floor(std::log2(v) / 3.0);
+}
+
+void load_locked()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    FILE *f = std::fopen(cache_path().c_str(), "r");
+    if (!f) return;
+    int S, cls, id;
+    double ms;
+    while (std::fscanf(f, "%d %d %d %lf", &S, &cls, &id, &ms) == 4)
+        if (id >= 0 && id < i8_tile_count() && i8_tile(id).S == S) g_table[{S, cls}] = id;
+    std::fclose(f);
+}
+
+void save_locked()
+{
+    const std::string path = cache_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        const std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    FILE *f = std::fopen(path.c_str(), "w");
+    if (!f) return;
+    for (auto &kv : g_table) std::fprintf(f, "%d %d %d 0\n", kv.first.first, kv.first.second, kv.second);
+    std::fclose(f);
+}
+} // namespace
+
+int autotune_i8(int S, int64_t m, int64_t n, int64_t k, int *best_tile, double *best_ms)
+{
+    if (S < 1 || S > 5) return fail(FF_EINVAL, "slices must be 1..5");
+    if (m < 1 || n < 1 || k < 1) return fail(FF_EINVAL, "sizes must be positive");
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = stream_of(nullptr);
+    // scratch sized for the largest padding of any candidate
+    int64_t amax = 0, bmax = 0;
+    const int64_t KP = round_up(k, I8_BK);
+    for (int id = 0; id < i8_tile_count(); ++id) {
+        const I8Tile &t = i8_tile(id);
+        if (t.S != S) continue;
+        amax = std::max(amax, round_up(m, t.bm()) * KP * S);
+        bmax = std::max(bmax, round_up(n, t.bn()) * KP * S);
+    }
+    int8_t *A = nullptr, *B = nullptr;
+    uint32_t *C = nullptr;
+    hipEvent_t e0, e1;
+    FF_HIP_CHECK(hipMalloc(&A, amax));
+    FF_HIP_CHECK(hipMalloc(&B, bmax));
+    FF_HIP_CHECK(hipMalloc(&C, m * n * 4));
+    FF_HIP_CHECK(hipMemsetAsync(A, 0x35, amax, st));
+    FF_HIP_CHECK(hipMemsetAsync(B, 0x53, bmax, st));
+    FF_HIP_CHECK(hipEventCreate(&e0));
+    FF_HIP_CHECK(hipEventCreate(&e1));
+    int best = -1;
+    double bms = 1e30;
+    for (int id = 0; id < i8_tile_count(); ++id) {
+        const I8Tile &t = i8_tile(id);
+        if (t.S != S) continue;
+        I8Job J;
+        std::memset(&J, 0, sizeof(J));
+        J.Ad = A; J.Bd = B;
+        J.a_plane = round_up(m, t.bm()) * KP;
+        J.b_plane = round_up(n, t.bn()) * KP;
+        J.C = C; J.ldc = n; J.m = (int)m; J.n = (int)n; J.KP = (int)KP; J.s = S;
+        J.p = 8388593; J.beta = 0; J.pd = 8388593.0; J.pinv = 1.0 / 8388593.0;
+        digit_weights(J.p, 1, 7, S, J.w);
+        J.tiles_m = (int)(round_up(m, t.bm()) / t.bm());
+        J.tiles_n = (int)(round_up(n, t.bn()) / t.bn());
+        FF_HIP_CHECK(launch_i8(id, J, st));
+        double ms_min = 1e30;
+        for (int r = 0; r < 3; ++r) {
+            FF_HIP_CHECK(hipEventRecord(e0, st));
+            FF_HIP_CHECK(launch_i8(id, J, st));
+            FF_HIP_CHECK(hipEventRecord(e1, st));
+            FF_HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0;
+            FF_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            ms_min = std::min(ms_min, (double)ms);
+        }
+        if (ms_min < bms) { bms = ms_min; best = id; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(A);
+    (void)hipFree(B);
+    (void)hipFree(C);
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        load_locked();
+        g_table[{S, size_class(m, n, k)}] = best;
+        save_locked();
+    }
+    if (best_tile) *best_tile = best;
+    if (best_ms) *best_ms = bms;
+    return FF_OK;
+}
+
+int tuned_i8_tile(int S, int64_t m, int64_t n, int64_t k)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    load_locked();
+    auto it = g_table.find({S, size_class(m, n, k)});
+    return it == g_table.end() ? -1 : it->second;
+}
+
+} // namespace ff
+
+using namespace ff;
+
+extern "C" int ff_autotune(int slices, int64_t m, int64_t n, int64_t k, int *best_tile,
+                           double *best_ms)
+{
+    return autotune_i8(slices, m, n, k, best_tile, best_ms);
+}

@@ -75,6 +75,8 @@ _SIGS = {
                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(_I64), ctypes.POINTER(_I64)], _INT),
     "ff_server_destroy": ([_VP], _INT),
+    "ff_autotune": ([_INT, _I64, _I64, _I64, ctypes.POINTER(_INT),
+                     ctypes.POINTER(ctypes.c_double)], _INT),
     "ff_profile_enable": ([_INT], _INT),
     "ff_profile_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)], _INT),
@@ -243,6 +245,12 @@ def ff_server_stats(server):
                                   ctypes.byref(gops), ctypes.byref(done), ctypes.byref(mx)))
     return {"p50_ms": p50.value, "p99_ms": p99.value, "gops": gops.value,
             "completed": done.value, "max_inflight": mx.value}
+
+
+def ff_autotune(slices, m, n, k):
+    best, ms = _INT(), ctypes.c_double()
+    _check(load().ff_autotune(slices, m, n, k, ctypes.byref(best), ctypes.byref(ms)))
+    return best.value, ms.value
 
 
 def ff_profile_enable(on):
