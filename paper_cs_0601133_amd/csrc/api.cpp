@@ -41,6 +41,14 @@ struct DevState {
     bool ok = false;
     std::string arch;
     std::map<hipStream_t, Buffer> ws;
+    std::map<hipStream_t, unsigned *> ctr;
+    struct Staging {
+        void *host = nullptr; // pinned
+        size_t bytes = 0;
+        hipEvent_t done = nullptr; // recorded after the last copy out of it
+        bool pending = false;
+    };
+    std::map<hipStream_t, Staging> stage;
 };
 
 std::mutex g_mu;
@@ -108,6 +116,59 @@ int workspace(hipStream_t st, size_t bytes, void **out)
     return FF_OK;
 }
 
+int counter_buffer(hipStream_t st, unsigned **out)
+{
+    int dev = 0;
+    FF_HIP_CHECK(hipGetDevice(&dev));
+    DevState *ds;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ds = g_devs[dev];
+    }
+    std::lock_guard<std::mutex> lk(ds->mu);
+    unsigned *&c = ds->ctr[st];
+    if (!c) {
+        FF_HIP_CHECK(hipMalloc(&c, 256));
+        FF_HIP_CHECK(hipMemset(c, 0, 256));
+    }
+    *out = c;
+    return FF_OK;
+}
+
+// Host -> device copy through a pinned per-stream buffer, so that the
+// caller's memory may be reused as soon as this returns and the copy stays
+// asynchronous.  The buffer is reused once its previous copy has completed.
+int upload_async(hipStream_t st, const void *src, size_t bytes, void *dst)
+{
+    int dev = 0;
+    FF_HIP_CHECK(hipGetDevice(&dev));
+    DevState *ds;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ds = g_devs[dev];
+    }
+    std::lock_guard<std::mutex> lk(ds->mu);
+    DevState::Staging &sg = ds->stage[st];
+    if (!sg.done) FF_HIP_CHECK(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
+    if (sg.pending) {
+        FF_HIP_CHECK(hipEventSynchronize(sg.done));
+        sg.pending = false;
+    }
+    if (sg.bytes < bytes) {
+        if (sg.host) FF_HIP_CHECK(hipHostFree(sg.host));
+        sg.host = nullptr;
+        sg.bytes = 0;
+        const size_t want = std::max<size_t>(bytes, 64 << 10);
+        FF_HIP_CHECK(hipHostMalloc(&sg.host, want, hipHostMallocDefault));
+        sg.bytes = want;
+    }
+    std::memcpy(sg.host, src, bytes);
+    FF_HIP_CHECK(hipMemcpyAsync(dst, sg.host, bytes, hipMemcpyHostToDevice, st));
+    FF_HIP_CHECK(hipEventRecord(sg.done, st));
+    sg.pending = true;
+    return FF_OK;
+}
+
 int release_all()
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -121,6 +182,19 @@ int release_all()
             }
         }
         ds->ws.clear();
+        for (auto &c : ds->ctr) {
+            (void)hipStreamSynchronize(c.first);
+            (void)hipFree(c.second);
+        }
+        ds->ctr.clear();
+        for (auto &sg : ds->stage) {
+            if (sg.second.done) {
+                (void)hipEventSynchronize(sg.second.done);
+                (void)hipEventDestroy(sg.second.done);
+            }
+            if (sg.second.host) (void)hipHostFree(sg.second.host);
+        }
+        ds->stage.clear();
     }
     return FF_OK;
 }

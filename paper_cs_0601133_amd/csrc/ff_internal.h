@@ -162,35 +162,42 @@ hipError_t launch_validate(const uint32_t *X, int64_t ld, int64_t rows,
                            int64_t cols, uint32_t p, unsigned *bad,
                            hipStream_t st);
 
-// Winograd pre-additions of one operand over L levels (see winograd.cpp).
-struct PreaddJob {
-    const uint32_t *X;   // residues, logical rows x cols of op(X)
+// One level of Winograd pre-additions for one operand side: each of the
+// count_in input operands (2*rows x 2*cols) gives seven operands (rows x
+// cols) in product order P1..P7 (A side: A11, A12, S4, A22, S1, S2, S3; B
+// side: B11, B21, B22, T4, T1, T2, T3; Appendix A).  Input: the caller's
+// residues (level 1, centered on load, op() applied) or int32 operands of
+// the previous level; output: int32, optionally reduced to centered
+// residues.
+struct PreLevel {
+    const void *X;
     int64_t ldx;
-    int trans;
-    int rows, cols;      // leaf block size: (full rows) / 2^L, (full cols) / 2^L
-    int L;
-    int side;            // 0: A-side combinations, 1: B-side
-    int reduce;          // reduce each leaf value to a centered residue
+    int trans;          // level 1 only: element (r, c) at X[c*ldx + r]
+    int in_residue;     // 1: X holds uint32 residues (level 1)
+    int count_in;
+    int rows, cols;     // output operand size
+    int side;           // 0: A side, 1: B side
+    int reduce;
     uint32_t p;
-    int out_digits;      // 0: write int32 leaves, 1: write packed digit planes
-    int32_t *Y;          // int32 leaves: [7^L][rows][cols]
-    // digit output (out_digits): planes of leaf q at D + q * leaf_bytes
-    int8_t *D;
-    int64_t leaf_bytes;
-    int S, bits, RT, rows_pad, KP;
-    int64_t plane;
-    int transpose_out;   // B side: leaves stored transposed (cols x rows)
+    int32_t *Y;         // [count_in*7][rows][cols]
 };
-hipError_t launch_preadd(const PreaddJob &job, hipStream_t st);
+hipError_t launch_preadd(const PreLevel &job, hipStream_t st);
 
-struct PostaddJob {
-    const uint32_t *P;   // 7^L leaf products, each rows x cols, ld = cols
-    int rows, cols, L;
-    uint32_t *C;
-    int64_t ldc;
+// One level of post-additions: count_out groups of seven products P1..P7
+// (canonical residues, rows x cols each) give the four quadrants of a
+// (2*rows) x (2*cols) block: U1, U5, U6, U7 (mod p).  At the top level the
+// result is combined with C: C <- alpha*U + beta*C (mod p).
+struct PostLevel {
+    const uint32_t *P;  // [count_out*7][rows][cols]
+    int count_out;
+    int rows, cols;
+    uint32_t *Y;        // output blocks
+    int64_t ldy;        // row pitch of an output block
+    int64_t block_stride; // elements between consecutive output blocks
+    int final_level;
     uint32_t p, alpha, beta;
-    double pd, pinv;
+    double pinv;
 };
-hipError_t launch_postadd(const PostaddJob &job, hipStream_t st);
+hipError_t launch_postadd(const PostLevel &job, hipStream_t st);
 
 } // namespace ff

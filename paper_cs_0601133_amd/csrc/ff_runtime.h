@@ -8,6 +8,11 @@ namespace ff {
 
 int check_device();
 int workspace(hipStream_t st, size_t bytes, void **out);
+// 256-byte zeroed counter block per (device, stream) for persistent kernels,
+// which leave it zeroed.
+int counter_buffer(hipStream_t st, unsigned **out);
+// Asynchronous host -> device copy through pinned per-stream staging.
+int upload_async(hipStream_t st, const void *src, size_t bytes, void *dst);
 int release_all();
 hipStream_t stream_of(const ff_opts *o);
 void set_stream(hipStream_t s);
