@@ -28,9 +28,9 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src):
-    obj = os.path.join(OUT, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+def _compile(src, out_dir=OUT, defines=()):
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + [f"-D{d}" for d in defines] + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -39,19 +39,21 @@ def _compile(src):
     return obj
 
 
-def build(jobs=None):
-    os.makedirs(OUT, exist_ok=True)
+def build(jobs=None, defines=(), lib=LIB, out_dir=OUT):
+    """Compile every source and link lib.  defines: extra -D flags (kernel
+    experiments build into a separate out_dir/lib)."""
+    os.makedirs(out_dir, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, sources()))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, out_dir, defines), sources()))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + \
         ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def ensure_built():

@@ -252,6 +252,18 @@ void digit_weights(uint32_t p, uint32_t alpha, int bits, int S, uint32_t *w)
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
+void i8_weights(I8Job &J, uint32_t alpha, int bits)
+{
+    const int S = J.s;
+    digit_weights(J.p, alpha, S == 1 ? 8 : bits, S, J.w);
+    const double h = (double)(J.p / 2);
+    for (int t = 0; t < 2 * S - 1; ++t)
+        J.wc[t] = J.w[t] > J.p / 2 ? (double)J.w[t] - (double)J.p : (double)J.w[t];
+    // every |E_t mod p| <= p/2 + 1 after the floating-point reduction
+    const double bound = (2.0 * S - 1.0) * h * (h + 1.0) + (double)J.p;
+    J.fp_epi = bound <= 9007199254740992.0 ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // Plain (no Winograd) paths
 // ---------------------------------------------------------------------------
@@ -319,7 +331,8 @@ int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
         J.C = C; J.ldc = ldc; J.m = (int)m; J.n = (int)n; J.KP = KPc; J.s = P.slices;
         J.p = p; J.beta = k0 == 0 ? beta : 1u;
         J.pd = (double)p; J.pinv = 1.0 / (double)p;
-        digit_weights(p, alpha, P.slices == 1 ? 8 : P.bits, P.slices, J.w);
+        i8_weights(J, alpha, P.bits);
+        J.gm = t.GM;
         J.tiles_m = mp / t.bm(); J.tiles_n = np / t.bn();
         FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_i8(P.tile, J, st)));
     }

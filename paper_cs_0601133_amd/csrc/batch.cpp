@@ -86,7 +86,8 @@ int prep_batch(const std::vector<IJob> &jobs, int path, int tile, BatchPrep *out
             J.beta = j.beta;
             J.pd = (double)j.p;
             J.pinv = 1.0 / (double)j.p;
-            digit_weights(j.p, j.alpha, j.S == 1 ? 8 : j.bits, j.S, J.w);
+            i8_weights(J, j.alpha, j.bits);
+            J.gm = t.GM;
             J.tiles_m = mp / t.bm();
             J.tiles_n = np / t.bn();
             J.tile_start = tiles;

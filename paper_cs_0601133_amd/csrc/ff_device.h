@@ -77,4 +77,17 @@ __device__ __forceinline__ void grouped_tile(int t, int tiles_m, int tiles_n,
     *tn = in / gsz;
 }
 
+// Same with the group height chosen at run time.
+__device__ __forceinline__ void grouped_tile_rt(int t, int tiles_m, int tiles_n, int gm,
+                                                int *tm, int *tn)
+{
+    const int per_group = gm * tiles_n;
+    const int g = t / per_group;
+    const int first = g * gm;
+    const int gsz = (tiles_m - first) < gm ? (tiles_m - first) : gm;
+    const int in = t - g * per_group;
+    *tm = first + in % gsz;
+    *tn = in / gsz;
+}
+
 } // namespace ff

@@ -39,6 +39,8 @@ struct I8Tile {
     int S;      // digits per operand (compile-time in the kernel)
     int TM, TN; // 32x32 MFMA tiles per wave
     int WGM, WGN;
+    int KS;     // K bytes per LDS stage (32 or 64)
+    int GM;     // tile rows per group of the tile order (L2 reuse)
     int bm() const { return WGM * 32 * TM; }
     int bn() const { return WGN * 32 * TN; }
     int threads() const { return 64 * WGM * WGN; }
@@ -127,9 +129,15 @@ struct I8Job {
     uint32_t p, beta;
     double pd, pinv;
     uint32_t w[9];      // alpha * R^t mod p, t = 0 .. 2s-2
+    double wc[9];       // the same weights centered, as doubles
+    int fp_epi;         // recombine in binary64: (2s-1)(p/2)(p/2+1) + p <= 2^53
+    int gm;             // tile-order group height
     int tiles_m, tiles_n;
     int tile_start;
 };
+
+// Fills w, wc and fp_epi of an INT8 job for digit width bits.
+void i8_weights(I8Job &J, uint32_t alpha, int bits);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files)

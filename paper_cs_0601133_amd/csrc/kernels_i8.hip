@@ -98,46 +98,96 @@ __global__ __launch_bounds__(SLICE_THREADS) void k_slice_batched(
 // ---------------------------------------------------------------------------
 // GEMM on digit planes
 // ---------------------------------------------------------------------------
-template <int S, int TM, int TN, int WGM, int WGN>
+constexpr int LDS_LIMIT = 160 * 1024 - 1024; // leave room for small shared variables
+
+
+
+// Geometry of one K stage (64 bytes of K) for SE digits per operand.
+template <int SE, int TM, int TN, int WGM, int WGN, int KS>
 struct Cfg {
     static constexpr int BM = WGM * 32 * TM;
     static constexpr int BN = WGN * 32 * TN;
     static constexpr int NT = 64 * WGM * WGN;
     static constexpr int NW = WGM * WGN;
-    static constexpr int NSET = 2 * S - 1;
-    static constexpr int A_BYTES = S * BM * I8_BK; // one stage, all digits
-    static constexpr int B_BYTES = S * BN * I8_BK;
+    static constexpr int NSET = 2 * SE - 1;
+    static constexpr int A_BYTES = SE * BM * KS;
+    static constexpr int B_BYTES = SE * BN * KS;
     static constexpr int STAGE = A_BYTES + B_BYTES;
-    static constexpr int CHUNKS = STAGE / 1024; // 1 KB per wave load
+    static constexpr int CHUNKS = STAGE / 1024;           // 1 KB per wave load
+    static constexpr int PER_WAVE = (CHUNKS + NW - 1) / NW; // loads per wave (max)
     static_assert(STAGE % 1024 == 0, "stage must be whole 1 KB chunks");
-    static_assert((BM * I8_BK) % 1024 == 0 && (BN * I8_BK) % 1024 == 0, "digit blocks");
+    static_assert((BM * KS) % 1024 == 0 && (BN * KS) % 1024 == 0, "digit blocks");
+    static constexpr int H = KS / 32; // 32-deep matrix-core steps per stage
 };
 
-// Issue the direct-to-LDS loads of stage kt.
-template <class C>
-__device__ __forceinline__ void issue_stage(const I8Job &J, int tm, int tn,
-                                            int kt, int s, char *lds_stage,
-                                            int wave, int lane)
+// Stages in the LDS ring: as many as fit (at most 6, at least 2); NST - 1
+// stages are in flight while one is consumed.
+template <int S, int TM, int TN, int WGM, int WGN, int KS>
+struct Ring {
+    static constexpr int STAGE = Cfg<S, TM, TN, WGM, WGN, KS>::STAGE;
+    static constexpr int FIT = LDS_LIMIT / STAGE;
+    static constexpr int NST = FIT > 6 ? 6 : (FIT < 2 ? 2 : FIT);
+    static constexpr int BYTES = NST * STAGE;
+};
+
+// s_waitcnt needs an immediate: wait until at most n vector memory
+// operations of this wave are outstanding.
+__device__ __forceinline__ void wait_vm(int n)
 {
-    const char *Abase = (const char *)J.Ad + (int64_t)tm * C::BM * J.KP + (int64_t)kt * C::BM * I8_BK;
-    const char *Bbase = (const char *)J.Bd + (int64_t)tn * C::BN * J.KP + (int64_t)kt * C::BN * I8_BK;
-    constexpr int ABLK = C::BM * I8_BK, BBLK = C::BN * I8_BK;
-    for (int c = wave; c < C::CHUNKS; c += C::NW) {
-        const int off = c * 1024;
-        const char *src;
-        int d;
-        if (off < C::A_BYTES) {
-            d = off / ABLK;
-            src = Abase + (int64_t)d * J.a_plane + (off - d * ABLK);
-        } else {
-            const int o = off - C::A_BYTES;
-            d = o / BBLK;
-            src = Bbase + (int64_t)d * J.b_plane + (o - d * BBLK);
-        }
-        if (d < s)
+    switch (n) {
+#define FF_W(k) case k: asm volatile("s_waitcnt vmcnt(" #k ")" ::: "memory"); break;
+        FF_W(0) FF_W(1) FF_W(2) FF_W(3) FF_W(4) FF_W(5) FF_W(6) FF_W(7)
+        FF_W(8) FF_W(9) FF_W(10) FF_W(11) FF_W(12) FF_W(13) FF_W(14) FF_W(15)
+#undef FF_W
+    default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    }
+}
+
+// Workgroup barrier without the memory fence of __syncthreads (which would
+// make every wave drain all of its outstanding global loads, i.e. every
+// stage in flight).  Ordering is explicit instead: each wave waits for its
+// own loads of the stage with wait_vm before the barrier, and every read of
+// a ring slot feeds a matrix-core instruction issued before the barrier, so
+// the slot is free when the barrier completes.  The empty asm statements
+// keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void ring_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Issue the direct-to-LDS loads of stage kt; returns how many this wave
+// issued.
+template <class C>
+__device__ __forceinline__ int issue_stage(const I8Job &J, int tm, int tn, int kt,
+                                           char *lds_stage, int wave, int lane)
+{
+    constexpr int KS = C::H * 32;
+    const char *Abase = (const char *)J.Ad + (int64_t)tm * C::BM * J.KP + (int64_t)kt * C::BM * KS;
+    const char *Bbase = (const char *)J.Bd + (int64_t)tn * C::BN * J.KP + (int64_t)kt * C::BN * KS;
+    constexpr int ABLK = C::BM * KS, BBLK = C::BN * KS;
+    int issued = 0;
+#pragma unroll
+    for (int i = 0; i < C::PER_WAVE; ++i) {
+        const int c = wave + i * C::NW;
+        if (C::CHUNKS % C::NW == 0 || c < C::CHUNKS) {
+            const int off = c * 1024;
+            const char *src;
+            if (off < C::A_BYTES) {
+                const int d = off / ABLK;
+                src = Abase + (int64_t)d * J.a_plane + (off - d * ABLK);
+            } else {
+                const int o = off - C::A_BYTES;
+                const int d = o / BBLK;
+                src = Bbase + (int64_t)d * J.b_plane + (o - d * BBLK);
+            }
             __builtin_amdgcn_global_load_lds((const void *)(src + lane * 16),
                                              (lds_ptr)(lds_stage + off), 16, 0, 0);
+            ++issued;
+        }
     }
+    return issued;
 }
 
 __device__ __forceinline__ uint32_t mod_i32(int32_t e, uint32_t p, double pd, double pinv)
@@ -151,14 +201,15 @@ __device__ __forceinline__ uint32_t mod_i32(int32_t e, uint32_t p, double pd, do
     return (uint32_t)ri;
 }
 
-template <int S, int TM, int TN, int WGM, int WGN>
+// One output tile with SE digits per operand; smem holds NST stages of the
+// layout for SE digits (the ring is sized for the configuration's maximum).
+template <int SE, int TM, int TN, int WGM, int WGN, int KS, int NST>
 __device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
 {
-    using C = Cfg<S, TM, TN, WGM, WGN>;
+    using C = Cfg<SE, TM, TN, WGM, WGN, KS>;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * 32 * TM, wn0 = (wave % WGN) * 32 * TN;
-    const int s = J.s;
 
     v16i acc[C::NSET][TM][TN];
 #pragma unroll
@@ -170,53 +221,79 @@ __device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) acc[t][i][j][v] = 0;
 
-    const int nk = J.KP / I8_BK;
-    issue_stage<C>(J, tm, tn, 0, s, smem, wave, lane);
+    const int nk = J.KP / KS;
+    // prologue: stages 0 .. NST-2 in flight (stage indices past the end are
+    // clamped: those loads refill a free slot with data nobody reads)
+    int per_stage = 0;
+#pragma unroll
+    for (int st = 0; st < NST - 1; ++st)
+        per_stage = issue_stage<C>(J, tm, tn, st < nk ? st : nk - 1, smem + st * C::STAGE,
+                                   wave, lane);
 
     for (int kt = 0; kt < nk; ++kt) {
-        char *cur = smem + (kt & 1) * C::STAGE;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (kt + 1 < nk)
-            issue_stage<C>(J, tm, tn, kt + 1, s, smem + ((kt + 1) & 1) * C::STAGE, wave, lane);
+        // Stage kt has landed once at most the NST-2 later stages' loads of
+        // this wave are outstanding; after the barrier every wave's part is
+        // in LDS, and the slot of stage kt-1 is free for stage kt+NST-1.
+        wait_vm((NST - 2) * per_stage);
+        ring_barrier();
+        const char *cur = smem + (kt % NST) * C::STAGE;
+        // Fragments of the stage's 32-deep K steps: lane l reads its 16-byte
+        // group (row l%32, K half l/32) of each digit block.
+        v4i a[C::H][SE][TM], b[C::H][SE][TN];
 #pragma unroll
-        for (int h = 0; h < I8_BK / 32; ++h) {
+        for (int h = 0; h < C::H; ++h) {
             const int cidx = 2 * h + (lane >> 5);
-            v4i a[S][TM], b[S][TN];
 #pragma unroll
-            for (int d = 0; d < S; ++d) {
-                if (d < s) {
+            for (int d = 0; d < SE; ++d) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    a[h][d][i] = *(const v4i *)(cur + d * C::BM * KS +
+                                                (cidx * C::BM + wm0 + 32 * i + (lane & 31)) * 16);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    b[h][d][j] = *(const v4i *)(cur + C::A_BYTES + d * C::BN * KS +
+                                                (cidx * C::BN + wn0 + 32 * j + (lane & 31)) * 16);
+            }
+        }
+        const int nxt = kt + NST - 1;
+        issue_stage<C>(J, tm, tn, nxt < nk ? nxt : nk - 1, smem + (nxt % NST) * C::STAGE, wave,
+                       lane);
+#pragma unroll
+        for (int h = 0; h < C::H; ++h)
+#pragma unroll
+            for (int da = 0; da < SE; ++da)
+#pragma unroll
+                for (int db = 0; db < SE; ++db)
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
-                        a[d][i] = *(const v4i *)(cur + d * C::BM * I8_BK +
-                                                 (cidx * C::BM + wm0 + 32 * i + (lane & 31)) * 16);
 #pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        b[d][j] = *(const v4i *)(cur + C::A_BYTES + d * C::BN * I8_BK +
-                                                 (cidx * C::BN + wn0 + 32 * j + (lane & 31)) * 16);
-                }
-            }
+                        for (int j = 0; j < TN; ++j)
+                            acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                a[h][da][i], b[h][db][j], acc[da + db][i][j], 0, 0, 0);
+        // Schedule: the fragment reads first, then the next stage's loads
+        // spread between the matrix-core instructions so that no burst of
+        // memory instructions holds up the matrix core.
+        constexpr int NDS = C::H * SE * (TM + TN);
+        constexpr int NMF = C::H * SE * SE * TM * TN;
+        constexpr int NLD = C::PER_WAVE;
+        constexpr int GAP = NMF / (NLD + 1);
+        __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);
 #pragma unroll
-            for (int da = 0; da < S; ++da)
-#pragma unroll
-                for (int db = 0; db < S; ++db) {
-                    if (da < s && db < s) {
-#pragma unroll
-                        for (int i = 0; i < TM; ++i)
-#pragma unroll
-                            for (int j = 0; j < TN; ++j)
-                                acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                    a[da][i], b[db][j], acc[da + db][i][j], 0, 0, 0);
-                    }
-                }
+        for (int q = 0; q < NLD; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, GAP, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
         }
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF - NLD * GAP, 0);
     }
-    // Every wave must be done with the last stage before smem is reused by
-    // the next tile of a persistent workgroup.
+    // drain the (dummy) loads still in flight before the ring is left
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // every wave is done with the ring before a persistent workgroup reuses it
     __syncthreads();
 
     // Epilogue.  32 x 32 accumulator layout: lane holds column lane%32 and
-    // rows 8*(v/4) + 4*(lane/32) + v%4, v = 0..15.
+    // rows 8*(v/4) + 4*(lane/32) + v%4, v = 0..15.  With fp_epi the digit
+    // sums are recombined exactly in binary64 (centered weights, centered
+    // E_t mod p), else in 64-bit integers with a reduction per term.
     const int m0 = tm * C::BM, n0 = tn * C::BN;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -227,12 +304,23 @@ __device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
                 const int row = m0 + wm0 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int col = n0 + wn0 + 32 * j + (lane & 31);
                 if (row < J.m && col < J.n) {
-                    uint32_t r = 0;
+                    uint32_t r;
+                    if (J.fp_epi) {
+                        double sum = 0.0;
 #pragma unroll
-                    for (int t = 0; t < C::NSET; ++t)
-                        if (t < 2 * s - 1)
+                        for (int t = 0; t < C::NSET; ++t) {
+                            const double x = (double)acc[t][i][j][v];
+                            const double e = __builtin_fma(-__builtin_rint(x * J.pinv), J.pd, x);
+                            sum = __builtin_fma(J.wc[t], e, sum);
+                        }
+                        r = canon_f64(sum, J.pd, J.pinv, J.p);
+                    } else {
+                        r = 0;
+#pragma unroll
+                        for (int t = 0; t < C::NSET; ++t)
                             r = addmod(r, mulmod(J.w[t], mod_i32(acc[t][i][j][v], J.p, J.pd, J.pinv),
                                                  J.p, J.pinv), J.p);
+                    }
                     uint32_t *cp = J.C + (int64_t)row * J.ldc + col;
                     if (J.beta) r = addmod(r, mulmod(J.beta, *cp, J.p, J.pinv), J.p);
                     *cp = r;
@@ -246,28 +334,43 @@ struct Wpe {
     static constexpr int v = (WGM * WGN) / 4 > 0 ? (WGM * WGN) / 4 : 1;
 };
 
-template <int S, int TM, int TN, int WGM, int WGN>
+template <int S, int TM, int TN, int WGM, int WGN, int KS>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
                           amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
 void k_fgemm_i8(I8Job J)
 {
-    using C = Cfg<S, TM, TN, WGM, WGN>;
-    __shared__ __attribute__((aligned(1024))) char smem[2 * C::STAGE];
+    using R = Ring<S, TM, TN, WGM, WGN, KS>;
+    __shared__ __attribute__((aligned(1024))) char smem[R::BYTES];
     const int G = J.tiles_m * J.tiles_n;
     const int t = xcd_remap(blockIdx.x, G);
     int tm, tn;
-    grouped_tile<8>(t, J.tiles_m, J.tiles_n, &tm, &tn);
-    i8_tile<S, TM, TN, WGM, WGN>(J, tm, tn, smem);
+    grouped_tile_rt(t, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
+    i8_tile<S, TM, TN, WGM, WGN, KS, R::NST>(J, tm, tn, smem);
 }
 
-template <int S, int TM, int TN, int WGM, int WGN>
+// Batched: a job may use fewer digits than the configuration's S; the tile
+// body is specialised per digit count so that no matrix-core instruction is
+// predicated.
+template <int S, int TM, int TN, int WGM, int WGN, int KS, int NST>
+__device__ __forceinline__ void i8_tile_any(const I8Job &J, int tm, int tn, char *smem)
+{
+    if constexpr (S >= 1) {
+        if (J.s == S) {
+            i8_tile<S, TM, TN, WGM, WGN, KS, NST>(J, tm, tn, smem);
+            return;
+        }
+    }
+    if constexpr (S > 1) i8_tile_any<S - 1, TM, TN, WGM, WGN, KS, NST>(J, tm, tn, smem);
+}
+
+template <int S, int TM, int TN, int WGM, int WGN, int KS>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
                           amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
 void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
                         int persistent, unsigned *ctr)
 {
-    using C = Cfg<S, TM, TN, WGM, WGN>;
-    __shared__ __attribute__((aligned(1024))) char smem[2 * C::STAGE];
+    using R = Ring<S, TM, TN, WGM, WGN, KS>;
+    __shared__ __attribute__((aligned(1024))) char smem[R::BYTES];
     __shared__ int s_tile;
     int g = persistent ? 0 : (int)blockIdx.x;
     for (;;) {
@@ -285,8 +388,8 @@ void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
         }
         const I8Job J = jobs[lo];
         int tm, tn;
-        grouped_tile<8>(g - J.tile_start, J.tiles_m, J.tiles_n, &tm, &tn);
-        i8_tile<S, TM, TN, WGM, WGN>(J, tm, tn, smem);
+        grouped_tile_rt(g - J.tile_start, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
+        i8_tile_any<S, TM, TN, WGM, WGN, KS, R::NST>(J, tm, tn, smem);
         if (!persistent) break;
     }
     if (persistent && threadIdx.x == 0) {
@@ -299,16 +402,16 @@ void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
     }
 }
 
-template <int S, int TM, int TN, int WGM, int WGN>
+template <int S, int TM, int TN, int WGM, int WGN, int KS>
 hipError_t run_single(const I8Job &J, hipStream_t st)
 {
     const int G = J.tiles_m * J.tiles_n;
-    hipLaunchKernelGGL((k_fgemm_i8<S, TM, TN, WGM, WGN>), dim3(G), dim3(64 * WGM * WGN),
+    hipLaunchKernelGGL((k_fgemm_i8<S, TM, TN, WGM, WGN, KS>), dim3(G), dim3(64 * WGM * WGN),
                        0, st, J);
     return hipGetLastError();
 }
 
-template <int S, int TM, int TN, int WGM, int WGN>
+template <int S, int TM, int TN, int WGM, int WGN, int KS>
 hipError_t run_batched(const I8Job *jobs, int njobs, int total, int persistent,
                        unsigned *ctr, hipStream_t st)
 {
@@ -320,39 +423,41 @@ hipError_t run_batched(const I8Job *jobs, int njobs, int total, int persistent,
         grid = cus < total ? cus : total;
         if (grid < 1) grid = 1;
     }
-    hipLaunchKernelGGL((k_fgemm_i8_batched<S, TM, TN, WGM, WGN>), dim3(grid),
+    hipLaunchKernelGGL((k_fgemm_i8_batched<S, TM, TN, WGM, WGN, KS>), dim3(grid),
                        dim3(64 * WGM * WGN), 0, st, jobs, njobs, total, persistent, ctr);
     return hipGetLastError();
 }
 
 } // namespace
 
-// Compiled configurations: id, S, TM, TN, WGM, WGN.  Each (WGM x WGN)
-// workgroup of 64-lane waves owns a (WGM*32*TM) x (WGN*32*TN) tile of C;
-// 2S-1 accumulator sets of TM*TN 32x32 blocks live in each wave.
+// Compiled configurations: id, S, TM, TN, WGM, WGN, KS, GM.  Each
+// (WGM x WGN) workgroup of 64-lane waves owns a (WGM*32*TM) x (WGN*32*TN)
+// tile of C; 2S-1 accumulator sets of TM*TN 32x32 blocks live in each wave;
+// KS bytes of K per LDS stage; GM tile rows per group of the tile order.
 #define FF_I8_TILES(X)                                                            \
-    X(0, 1, 2, 2, 2, 2)  /* 128 x 128, 4 waves,   64 acc */                        \
-    X(1, 1, 2, 2, 4, 2)  /* 256 x 128, 8 waves,   64 acc */                        \
-    X(2, 1, 2, 4, 2, 2)  /* 128 x 256, 4 waves,  128 acc */                        \
-    X(3, 2, 2, 2, 2, 2)  /* 128 x 128, 4 waves,  192 acc */                        \
-    X(4, 2, 1, 2, 4, 2)  /* 128 x 128, 8 waves,   96 acc */                        \
-    X(5, 3, 1, 2, 4, 1)  /* 128 x  64, 4 waves,  160 acc */                        \
-    X(6, 3, 1, 2, 4, 2)  /* 128 x 128, 8 waves,  160 acc */                        \
-    X(7, 3, 1, 1, 4, 2)  /* 128 x  64, 8 waves,   80 acc */                        \
-    X(8, 4, 1, 1, 4, 2)  /* 128 x  64, 8 waves,  112 acc */                        \
-    X(9, 4, 1, 1, 2, 2)  /*  64 x  64, 4 waves,  112 acc */                        \
-    X(10, 4, 1, 1, 2, 4) /*  64 x 128, 8 waves,  112 acc */                        \
-    X(11, 5, 1, 1, 4, 1) /* 128 x  32, 4 waves,  144 acc */                        \
-    X(12, 5, 1, 1, 4, 2) /* 128 x  64, 8 waves,  144 acc */
+    X(0, 1, 2, 2, 2, 2, 64, 8)  /* 128 x 128, 4 waves,   64 acc */                \
+    X(1, 1, 2, 2, 4, 2, 64, 8)  /* 256 x 128, 8 waves,   64 acc */                \
+    X(2, 1, 2, 2, 4, 2, 32, 8)  /* 256 x 128, 8 waves, half stages */             \
+    X(3, 2, 1, 2, 4, 2, 32, 8)  /* 128 x 128, 8 waves,   96 acc, half stages */   \
+    X(4, 2, 1, 2, 4, 2, 64, 8)  /* 128 x 128, 8 waves,   96 acc */                \
+    X(5, 3, 1, 2, 4, 2, 32, 8)  /* 128 x 128, 8 waves,  160 acc, half stages */   \
+    X(6, 3, 1, 2, 4, 2, 64, 8)  /* 128 x 128, 8 waves,  160 acc */                \
+    X(7, 3, 1, 1, 4, 2, 64, 8)  /* 128 x  64, 8 waves,   80 acc */                \
+    X(8, 4, 1, 1, 4, 2, 64, 8)  /* 128 x  64, 8 waves,  112 acc */                \
+    X(9, 4, 1, 1, 4, 2, 64, 4)  /* 128 x  64, 8 waves,  groups of 4 */            \
+    X(10, 4, 1, 1, 2, 4, 64, 8) /*  64 x 128, 8 waves,  112 acc */                \
+    X(11, 4, 1, 1, 4, 2, 32, 4) /* 128 x  64, half stages, groups of 4 */         \
+    X(12, 5, 1, 1, 4, 2, 64, 8) /* 128 x  64, 8 waves,  144 acc */                \
+    X(13, 4, 1, 1, 4, 2, 32, 8) /* 128 x  64, half stages */
 
 namespace {
 const I8Tile k_tiles[] = {
-#define FF_ROW(id, S, TM, TN, WGM, WGN) I8Tile{id, S, TM, TN, WGM, WGN},
+#define FF_ROW(id, S, TM, TN, WGM, WGN, KS, GM) I8Tile{id, S, TM, TN, WGM, WGN, KS, GM},
     FF_I8_TILES(FF_ROW)
 #undef FF_ROW
 };
 // Default configuration per slice count (index = S).
-const int k_default[6] = {-1, 0, 4, 6, 8, 12};
+const int k_default[6] = {-1, 1, 4, 6, 8, 12};
 } // namespace
 
 int i8_tile_count() { return (int)(sizeof(k_tiles) / sizeof(k_tiles[0])); }
@@ -362,8 +467,8 @@ int i8_default_tile(int S) { return (S >= 1 && S <= 5) ? k_default[S] : -1; }
 hipError_t launch_i8(int tile, const I8Job &J, hipStream_t st)
 {
     switch (tile) {
-#define FF_CASE(id, S, TM, TN, WGM, WGN)                                            \
-    case id: return run_single<S, TM, TN, WGM, WGN>(J, st);
+#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM)                                    \
+    case id: return run_single<S, TM, TN, WGM, WGN, KS>(J, st);
         FF_I8_TILES(FF_CASE)
 #undef FF_CASE
     default: return hipErrorInvalidValue;
@@ -374,8 +479,8 @@ hipError_t launch_i8_batched(int tile, const I8Job *jobs, int njobs, int total,
                              int persistent, unsigned *ctr, hipStream_t st)
 {
     switch (tile) {
-#define FF_CASE(id, S, TM, TN, WGM, WGN)                                            \
-    case id: return run_batched<S, TM, TN, WGM, WGN>(jobs, njobs, total, persistent, ctr, st);
+#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM)                                    \
+    case id: return run_batched<S, TM, TN, WGM, WGN, KS>(jobs, njobs, total, persistent, ctr, st);
         FF_I8_TILES(FF_CASE)
 #undef FF_CASE
     default: return hipErrorInvalidValue;

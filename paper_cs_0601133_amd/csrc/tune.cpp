@@ -113,7 +113,8 @@ int autotune_i8(int S, int64_t m, int64_t n, int64_t k, int *best_tile, double *
         J.b_plane = round_up(n, t.bn()) * KP;
         J.C = C; J.ldc = n; J.m = (int)m; J.n = (int)n; J.KP = (int)KP; J.s = S;
         J.p = 8388593; J.beta = 0; J.pd = 8388593.0; J.pinv = 1.0 / 8388593.0;
-        digit_weights(J.p, 1, 7, S, J.w);
+        i8_weights(J, 1, 7);
+        J.gm = t.GM;
         J.tiles_m = (int)(round_up(m, t.bm()) / t.bm());
         J.tiles_n = (int)(round_up(n, t.bn()) / t.bn());
         FF_HIP_CHECK(launch_i8(id, J, st));

@@ -89,7 +89,9 @@ _lib = None
 
 
 def library_path():
-    return _build.LIB
+    # FF_LIBRARY points at another build of the same library (kernel
+    # experiments); the default is the in-tree build.
+    return os.environ.get("FF_LIBRARY") or _build.LIB
 
 
 def load():
