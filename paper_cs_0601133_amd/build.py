@@ -23,6 +23,12 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wno-pass-failed", "-I", CSRC]
 
 
+# Per-source flags.  The FP64 kernels fold their accumulators with vector
+# ALU code between matrix-core steps; with accumulators in AGPRs the
+# compiler would move all of them to VGPRs and back around every fold.
+PER_FILE = {"kernels_f64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
@@ -30,7 +36,8 @@ def sources():
 
 def _compile(src, out_dir=OUT, defines=()):
     obj = os.path.join(out_dir, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + [f"-D{d}" for d in defines] + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + PER_FILE.get(os.path.basename(src), []) + \
+        [f"-D{d}" for d in defines] + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

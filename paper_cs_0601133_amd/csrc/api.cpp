@@ -264,26 +264,54 @@ void i8_weights(I8Job &J, uint32_t alpha, int bits)
     J.fp_epi = bound <= 9007199254740992.0 ? 1 : 0;
 }
 
+// Packing task of one operand into centered doubles (row tile RT).
+SliceJob pack_job(const void *X, int64_t ldx, int rows, int K, int trans, int in_mode,
+                  uint32_t p, double *D, int RT, int KP)
+{
+    SliceJob s = slice_job(X, ldx, rows, K, trans, in_mode, p, 0, 0, (int8_t *)D, RT, KP);
+    s.plane = (int64_t)s.rows_pad * KP * 8;
+    return s;
+}
+
+// FP64 GEMM job on packed operands; kblock products fit between reductions.
+F64Job f64_job(const double *Ad, const double *Bd, uint32_t *C, int64_t ldc, int64_t m,
+               int64_t n, int KP, uint32_t p, uint32_t alpha, uint32_t beta, int64_t kblock,
+               int tile)
+{
+    const F64Tile &t = f64_tile(tile);
+    F64Job J;
+    std::memset(&J, 0, sizeof(J));
+    J.Ad = Ad; J.Bd = Bd; J.C = C; J.ldc = ldc;
+    J.m = (int)m; J.n = (int)n; J.KP = KP;
+    J.p = p; J.alpha = alpha; J.beta = beta;
+    J.pd = (double)p; J.pinv = 1.0 / (double)p;
+    // a stage adds F64_BK products to every partial sum
+    J.fold_stages = (int)std::min<int64_t>(kblock / F64_BK, 0x3FFFFFFF);
+    J.gm = t.GM;
+    J.tiles_m = (int)((m + t.bm() - 1) / t.bm());
+    J.tiles_n = (int)((n + t.bn() - 1) / t.bn());
+    return J;
+}
+
 // ---------------------------------------------------------------------------
 // Plain (no Winograd) paths
 // ---------------------------------------------------------------------------
 int run_f64_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
                   uint32_t alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
                   uint32_t beta, uint32_t *C, int64_t ldc, int in_mode, int64_t kblock,
-                  hipStream_t st)
+                  int tile, void *ws, hipStream_t st)
 {
-    F64Job J;
-    std::memset(&J, 0, sizeof(J));
-    J.A = A; J.B = B; J.C = C;
-    J.lda = lda; J.ldb = ldb; J.ldc = ldc;
-    J.m = (int)m; J.n = (int)n; J.k = (int)k;
-    J.transA = transA; J.transB = transB; J.in_mode = in_mode;
-    J.p = p; J.alpha = alpha; J.beta = beta;
-    J.pd = (double)p; J.pinv = 1.0 / (double)p;
-    J.fold_every = (int)std::min<int64_t>(kblock / 4, 0x3FFFFFFF);
-    J.tiles_m = (int)((m + F64_BM - 1) / F64_BM);
-    J.tiles_n = (int)((n + F64_BN - 1) / F64_BN);
-    FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_f64(J, st)));
+    const F64Tile &t = f64_tile(tile);
+    const int KP = (int)round_up(k, F64_BK);
+    double *Ad = (double *)ws;
+    double *Bd = Ad + round_up(m, t.bm()) * KP;
+    // A: rows m, element (i, l) of op(A); B^T: rows n, element (j, l) = op(B)(l, j)
+    SliceJob sa = pack_job(A, lda, (int)m, (int)k, transA, in_mode, p, Ad, t.bm(), KP);
+    SliceJob sb = pack_job(B, ldb, (int)n, (int)k, transB ? 0 : 1, in_mode, p, Bd, t.bn(), KP);
+    FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_pack_f64(sa, st)));
+    FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_pack_f64(sb, st)));
+    F64Job J = f64_job(Ad, Bd, C, ldc, m, n, KP, p, alpha, beta, kblock, tile);
+    FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_f64(tile, J, st)));
     return FF_OK;
 }
 
@@ -433,11 +461,11 @@ int ff_fgemm_ex(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_
     if (P.levels > 0)
         return run_winograd(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                             P, o, st);
-    if (P.path == FF_PATH_FP64)
-        return run_f64_plain(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
-                             IN_RESIDUE, P.kblock, st);
     void *ws = nullptr;
     if ((rc = workspace(st, (size_t)P.ws_bytes, &ws))) return rc;
+    if (P.path == FF_PATH_FP64)
+        return run_f64_plain(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                             IN_RESIDUE, P.kblock, P.tile, ws, st);
     return run_i8_plain(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, P,
                         ws, st);
 }

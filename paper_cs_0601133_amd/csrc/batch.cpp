@@ -21,8 +21,6 @@ namespace {
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
-int flag_key(int ta, int tb, int mode) { return ta * 4 + tb * 2 + mode; }
-
 } // namespace
 
 int prep_batch(const std::vector<IJob> &jobs, int path, int tile, BatchPrep *out)
@@ -97,25 +95,47 @@ int prep_batch(const std::vector<IJob> &jobs, int path, int tile, BatchPrep *out
         B.slice_blocks = blocks;
         B.i8_tiles = tiles;
     } else {
-        std::stable_sort(work.begin(), work.end(),
-                         [](const IJob &a, const IJob &b) { return a.k > b.k; });
+        const F64Tile &t = f64_tile(tile);
+        // jobs reduced per stage before jobs reduced after every step (two
+        // launches), heaviest tiles first within each group
+        auto fine = [](const IJob &j) { return j.kblock < F64_BK; };
+        std::stable_sort(work.begin(), work.end(), [&](const IJob &a, const IJob &b) {
+            if (fine(a) != fine(b)) return !fine(a);
+            return a.k > b.k;
+        });
+        int blocks = 0, tiles = 0;
+        B.fj_fine = (int)work.size();
         for (const IJob &j : work) {
-            F64Job J;
-            std::memset(&J, 0, sizeof(J));
-            J.A = j.A; J.B = j.B; J.C = j.C;
-            J.lda = j.lda; J.ldb = j.ldb; J.ldc = j.ldc;
-            J.m = (int)j.m; J.n = (int)j.n; J.k = (int)j.k;
-            J.transA = j.ta; J.transB = j.tb; J.in_mode = j.in_mode;
-            J.p = j.p; J.alpha = j.alpha; J.beta = j.beta;
-            J.pd = (double)j.p; J.pinv = 1.0 / (double)j.p;
-            J.fold_every = (int)std::min<int64_t>(j.kblock / 4, 0x3FFFFFFF);
-            J.tiles_m = (int)((j.m + F64_BM - 1) / F64_BM);
-            J.tiles_n = (int)((j.n + F64_BN - 1) / F64_BN);
-            const int key = flag_key(j.ta, j.tb, j.in_mode);
-            J.tile_start = B.f64_tiles[key];
-            B.f64_tiles[key] += J.tiles_m * J.tiles_n;
-            B.fj[key].push_back(J);
+            if (fine(j) && B.fj_fine == (int)work.size()) {
+                B.fj_fine = (int)B.fj.size();
+                B.f64_tiles[0] = tiles;
+                tiles = 0;
+            }
+            const int KP = (int)round_up(j.k, F64_BK);
+            const int64_t mp = round_up(j.m, t.bm()), np = round_up(j.n, t.bn());
+            const int64_t a_off = planes;
+            planes = align256(planes + mp * KP * 8);
+            const int64_t b_off = planes;
+            planes = align256(planes + np * KP * 8);
+            // packed operands are relative offsets until the workspace is known
+            SliceJob sa = pack_job(j.A, j.lda, (int)j.m, (int)j.k, j.ta, j.in_mode, j.p,
+                                   (double *)(intptr_t)a_off, t.bm(), KP);
+            SliceJob sb = pack_job(j.B, j.ldb, (int)j.n, (int)j.k, j.tb ? 0 : 1, j.in_mode, j.p,
+                                   (double *)(intptr_t)b_off, t.bn(), KP);
+            sa.block_start = blocks;
+            blocks += pack_blocks(sa);
+            sb.block_start = blocks;
+            blocks += pack_blocks(sb);
+            B.sj.push_back(sa);
+            B.sj.push_back(sb);
+            F64Job J = f64_job((const double *)(intptr_t)a_off, (const double *)(intptr_t)b_off,
+                               j.C, j.ldc, j.m, j.n, KP, j.p, j.alpha, j.beta, j.kblock, tile);
+            J.tile_start = tiles;
+            tiles += J.tiles_m * J.tiles_n;
+            B.fj.push_back(J);
         }
+        B.slice_blocks = blocks;
+        B.f64_tiles[B.fj_fine < (int)B.fj.size() ? 1 : 0] = tiles;
     }
     // workspace layout: tables, then digit planes
     int64_t off = 0;
@@ -123,10 +143,8 @@ int prep_batch(const std::vector<IJob> &jobs, int path, int tile, BatchPrep *out
     off = align256(off + (int64_t)B.sj.size() * sizeof(SliceJob));
     B.off_ij = off;
     off = align256(off + (int64_t)B.ij.size() * sizeof(I8Job));
-    for (int g = 0; g < 8; ++g) {
-        B.off_fj[g] = off;
-        off = align256(off + (int64_t)B.fj[g].size() * sizeof(F64Job));
-    }
+    B.off_fj = off;
+    off = align256(off + (int64_t)B.fj.size() * sizeof(F64Job));
     B.table_bytes = off;
     B.off_planes = off;
     B.ws_bytes = off + planes;
@@ -146,12 +164,14 @@ static void bind_tables(BatchPrep &B, char *ws)
         J.Ad = (const int8_t *)(planes + (intptr_t)J.Ad);
         J.Bd = (const int8_t *)(planes + (intptr_t)J.Bd);
     }
+    std::vector<F64Job> fj = B.fj;
+    for (auto &J : fj) {
+        J.Ad = (const double *)(planes + (intptr_t)J.Ad);
+        J.Bd = (const double *)(planes + (intptr_t)J.Bd);
+    }
     if (!sj.empty()) std::memcpy(B.staging.data() + B.off_sj, sj.data(), sj.size() * sizeof(SliceJob));
     if (!ij.empty()) std::memcpy(B.staging.data() + B.off_ij, ij.data(), ij.size() * sizeof(I8Job));
-    for (int g = 0; g < 8; ++g)
-        if (!B.fj[g].empty())
-            std::memcpy(B.staging.data() + B.off_fj[g], B.fj[g].data(),
-                        B.fj[g].size() * sizeof(F64Job));
+    if (!fj.empty()) std::memcpy(B.staging.data() + B.off_fj, fj.data(), fj.size() * sizeof(F64Job));
     B.bound_ws = ws;
 }
 
@@ -182,12 +202,20 @@ int launch_batch(BatchPrep &B, unsigned *ctr, hipStream_t st, int persistent)
                                                 (int)B.ij.size(), B.i8_tiles, persistent, ctr,
                                                 st)));
     }
-    for (int g = 0; g < 8; ++g) {
-        if (B.fj[g].empty()) continue;
-        FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st,
-                              launch_f64_batched((const F64Job *)(ws + B.off_fj[g]),
-                                                 (int)B.fj[g].size(), B.f64_tiles[g], persistent,
-                                                 ctr, (g >> 2) & 1, (g >> 1) & 1, g & 1, st)));
+    if (B.path == FF_PATH_FP64 && !B.fj.empty()) {
+        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st,
+                              launch_pack_f64_batched((const SliceJob *)(ws + B.off_sj),
+                                                      (int)B.sj.size(), B.slice_blocks, st)));
+        const F64Job *tab = (const F64Job *)(ws + B.off_fj);
+        const int nf = (int)B.fj.size() - B.fj_fine;
+        if (B.fj_fine > 0)
+            FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st,
+                                  launch_f64_batched(B.tile, tab, B.fj_fine, B.f64_tiles[0],
+                                                     persistent, ctr, 0, st)));
+        if (nf > 0)
+            FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st,
+                                  launch_f64_batched(B.tile, tab + B.fj_fine, nf, B.f64_tiles[1],
+                                                     persistent, ctr, 1, st)));
     }
     return FF_OK;
 }
@@ -247,10 +275,12 @@ int prep_abi_batch(const ff_job *jobs, int njobs, const ff_opts &o, BatchPrep *B
         if (j.m * j.n * j.k > big_m * big_n * big_k) { big_m = j.m; big_n = j.n; big_k = j.k; }
         v.push_back(j);
     }
-    int tile = -1;
+    int tile;
     if (path == FF_PATH_INT8) {
         tile = tuned_i8_tile(Smax, big_m, big_n, big_k);
         if (tile < 0) tile = i8_default_tile(Smax);
+    } else {
+        tile = choose_f64_tile();
     }
     return prep_batch(v, path, tile, B);
 }

@@ -28,15 +28,15 @@ struct IJob {
 
 struct BatchPrep {
     int path = FF_PATH_INT8;
-    int tile = -1;
-    std::vector<SliceJob> sj;
+    int tile = -1;             // INT8 or FP64 tile configuration
+    std::vector<SliceJob> sj;  // digit slicing (INT8) or packing (FP64) tasks
     std::vector<I8Job> ij;
-    std::vector<F64Job> fj[8]; // grouped by transposes and input mode
-    int f64_tiles[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int slice_blocks = 0, i8_tiles = 0;
+    std::vector<F64Job> fj;    // jobs reduced per stage, then jobs reduced per step
+    int fj_fine = 0;           // index of the first per-step job in fj
+    int slice_blocks = 0, i8_tiles = 0, f64_tiles[2] = {0, 0};
     std::vector<IJob> scales;  // k == 0 or alpha == 0: C <- beta*C
     std::vector<IJob> singles; // longer than one int32 pass: run alone
-    int64_t off_sj = 0, off_ij = 0, off_fj[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t off_sj = 0, off_ij = 0, off_fj = 0;
     int64_t off_planes = 0, table_bytes = 0, ws_bytes = 0;
     std::vector<char> staging; // serialised tables bound to a workspace
     char *bound_ws = nullptr;

@@ -27,8 +27,25 @@ int fail(int status, const std::string &msg);
 // ---------------------------------------------------------------------------
 // Tile configurations
 // ---------------------------------------------------------------------------
-// FP64 kernel: 128 x 128 output tile per workgroup of 256 threads, K step 16.
-constexpr int F64_BM = 128, F64_BN = 128, F64_BK = 16, F64_THREADS = 256;
+// FP64 kernel: operands packed as centered doubles, K step 16, waves of 64
+// lanes each owning 64 x 64 outputs, WGM x WGN waves per workgroup, NST
+// LDS stages.  Several configurations are compiled; the planner picks one.
+constexpr int F64_BK = 16;
+struct F64Tile {
+    int id;
+    int WGM, WGN;
+    int NST;    // LDS ring stages
+    int WPE;    // waves per SIMD the kernel is built for
+    int GM;     // tile rows per group of the tile order
+    int bm() const { return 64 * WGM; }
+    int bn() const { return 64 * WGN; }
+    int threads() const { return 64 * WGM * WGN; }
+};
+int f64_tile_count();
+const F64Tile &f64_tile(int id);
+int f64_default_tile();
+// The configuration the planner uses (FF_F64_TILE overrides the default).
+int choose_f64_tile();
 
 // INT8 kernel: workgroup tile BM x BN, K step 64 bytes, waves of 64 lanes
 // each owning (32*TM) x (32*TN) outputs.  Several configurations per slice
@@ -83,22 +100,30 @@ inline int64_t centered_hi(uint32_t p) { return (int64_t)((p - 1) / 2); }
 // ---------------------------------------------------------------------------
 // Device job descriptors
 // ---------------------------------------------------------------------------
-// Operand of the FP64 kernel: uint32 residues centered on load, or int32
-// values already centered (Winograd leaves).
+// Operand of the packing kernels: uint32 residues (centered while packing)
+// or int32 values already centered (Winograd leaves).
 enum { IN_RESIDUE = 0, IN_SIGNED = 1 };
 
+// FP64 GEMM job on packed double operands.  An operand with rows r (m
+// index of op(A), n index of op(B)), K index k and row tile RT holds the
+// centered value of element (r, k) at double offset
+//     (r/RT)*RT*KP + (k/16)*RT*16 + ((r%RT)/16)*256 + ((k%16)/2)*32
+//       + (r%16)*2 + k%2,
+// zero padded to rows_pad x KP: each K stage of a row tile is one contiguous
+// block, and inside it the two consecutive K values that a lane feeds to two
+// matrix-core steps are one 16-byte word.
 struct F64Job {
-    const void *A;
-    const void *B;
+    const double *Ad;   // op(A) packed with row tile bm
+    const double *Bd;   // op(B)^T packed with row tile bn
     uint32_t *C;
-    int64_t lda, ldb, ldc;
-    int m, n, k;
-    int transA, transB, in_mode;
+    int64_t ldc;
+    int m, n, KP;       // KP: K padded to a multiple of F64_BK
     uint32_t p, alpha, beta;
     double pd, pinv;
-    int fold_every;  // MFMA k-substeps (4 products each) between reductions
+    int fold_stages;    // K stages between reductions; 0: after every 4-product step
+    int gm;             // tile-order group height
     int tiles_m, tiles_n;
-    int tile_start;  // first global tile index of this job (batched launches)
+    int tile_start;     // first global tile index of this job (batched launches)
 };
 
 // Slicing task: one operand of one job into packed digit planes.
@@ -109,11 +134,11 @@ struct SliceJob {
     int trans;          // element (r, c) at X[c*ldx + r] instead of X[r*ldx + c]
     int in_mode;        // IN_RESIDUE (center with p) or IN_SIGNED
     uint32_t p;
-    int S, bits;
+    int S, bits;        // S == 0: one plane of doubles for the FP64 kernel
     int8_t *D;          // packed planes
     int RT;             // row tile of the packing
     int rows_pad, KP;   // padded sizes
-    int64_t plane;      // bytes per digit plane = rows_pad * KP
+    int64_t plane;      // bytes per digit plane = rows_pad * KP (x 8 for doubles)
     int block_start;    // first global block of this task
 };
 
@@ -142,15 +167,18 @@ void i8_weights(I8Job &J, uint32_t alpha, int bits);
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
-// Single-job FP64 fgemm: job passed by value.
-hipError_t launch_f64(const F64Job &job, hipStream_t st);
-// Batched FP64: device job table; grid = total tiles (persistent == 0) or a
-// persistent grid draining a tile counter (ctr: 2 words, zero on entry, left
-// at zero on exit).
-// All jobs of one table share transposes (ta, tb) and input mode.
-hipError_t launch_f64_batched(const F64Job *dev_jobs, int njobs, int total_tiles,
-                              int persistent, unsigned *ctr, int ta, int tb, int mode,
-                              hipStream_t st);
+// FP64 GEMM on packed operands with tile configuration `tile`: one job
+// passed by value, or a device job table; grid = total tiles (persistent ==
+// 0) or a persistent grid draining a tile counter (ctr: 2 words, zero on
+// entry, left at zero on exit).  In a table either every job has
+// fold_stages == 0 (fine != 0) or none has.
+hipError_t launch_f64(int tile, const F64Job &job, hipStream_t st);
+hipError_t launch_f64_batched(int tile, const F64Job *dev_jobs, int njobs, int total_tiles,
+                              int persistent, unsigned *ctr, int fine, hipStream_t st);
+// Operand -> packed centered doubles (SliceJob with S == 0).
+hipError_t launch_pack_f64(const SliceJob &job, hipStream_t st);
+hipError_t launch_pack_f64_batched(const SliceJob *dev_jobs, int njobs, int total_blocks,
+                                   hipStream_t st);
 
 hipError_t launch_slice(const SliceJob &job, hipStream_t st);
 hipError_t launch_slice_batched(const SliceJob *dev_jobs, int njobs,

@@ -25,10 +25,17 @@ int64_t round_up(int64_t x, int64_t q);
 SliceJob slice_job(const void *X, int64_t ldx, int rows, int K, int trans, int in_mode,
                    uint32_t p, int S, int bits, int8_t *D, int RT, int KP);
 int slice_blocks(const SliceJob &J);
+SliceJob pack_job(const void *X, int64_t ldx, int rows, int K, int trans, int in_mode,
+                  uint32_t p, double *D, int RT, int KP);
+int pack_blocks(const SliceJob &J);
+F64Job f64_job(const double *Ad, const double *Bd, uint32_t *C, int64_t ldc, int64_t m,
+               int64_t n, int KP, uint32_t p, uint32_t alpha, uint32_t beta, int64_t kblock,
+               int tile);
+// ws: (round_up(m, bm) + round_up(n, bn)) * round_up(k, 16) doubles.
 int run_f64_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
                   uint32_t alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
                   uint32_t beta, uint32_t *C, int64_t ldc, int in_mode, int64_t kblock,
-                  hipStream_t st);
+                  int tile, void *ws, hipStream_t st);
 int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
                  uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
                  int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const Plan &P,

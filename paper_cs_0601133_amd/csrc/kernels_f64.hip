@@ -1,123 +1,128 @@
 // FP64 matrix-core fgemm: the "Zpz-double" design of Sections 2.1.2 and 3.1
-// (residues held as integer-valued doubles, products summed exactly by the
-// floating-point unit, reduction delayed) on gfx950's v_mfma_f64_16x16x4.
+// (residues converted to integer-valued doubles, products summed exactly by
+// the floating-point unit, reduction delayed) on gfx950's v_mfma_f64_16x16x4.
 //
-// Per workgroup: a 128 x 128 tile of C, 4 waves of 64 x 64, K in steps of 16.
-// Global -> registers (uint32 residues, centered on the way) -> LDS as
-// doubles (double buffered) -> MFMA operands.  Every fold_every MFMA steps
-// (4 products each) the accumulators are reduced to x - p*rint(x/p), which
-// keeps every partial sum an integer of magnitude <= kblock*max|ab| + p + 2
-// <= 2^53 and hence exact whatever order the matrix core adds in.  The
-// epilogue makes the residue canonical and applies alpha and beta modulo p.
+// Two kernels, as in the paper's scheme of converting the operands once and
+// then calling a floating-point matrix product:
+//   * packing: each operand is centered (|c| <= p/2) and written as doubles
+//     in a tile-packed layout (the F64Job comment in ff_internal.h), zero
+//     padded, transposition resolved;
+//   * GEMM: every K stage of a row tile is one contiguous block, copied
+//     straight into an LDS ring by global_load_lds (no register staging, no
+//     conversion work in the loop) and read back as one 16-byte word per lane
+//     and two matrix-core steps.  Each wave owns 64 x 64 outputs (16 blocks
+//     of 16 x 16) whose accumulators stay in VGPRs (the file is built with
+//     the MFMA VGPR form), so the periodic reduction x - p*rint(x/p) costs no
+//     register moves.  It runs often enough to keep every partial sum an
+//     integer of magnitude <= kblock*max|ab| + p + 2 <= 2^53, hence exact in
+//     whatever order the matrix core adds.  The epilogue makes the residue
+//     canonical and applies alpha and beta modulo p.
 #include "ff_device.h"
 #include "ff_internal.h"
+#include "ff_ring.h"
 
 namespace ff {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// Compiled configurations: id, WGM, WGN, NST, waves per SIMD, GM.
+#define FF_F64_TILES(X)                                                        \
+    X(0, 2, 2, 4, 1, 8)                                                        \
+    X(1, 4, 2, 3, 2, 8)                                                        \
+    X(2, 2, 2, 2, 2, 8)                                                        \
+    X(3, 2, 4, 3, 2, 8)
 
 namespace {
 
-constexpr int LDP = F64_BM + 16; // padded LDS row, in doubles
+// ---------------------------------------------------------------------------
+// Packing: operand -> centered doubles
+// ---------------------------------------------------------------------------
+constexpr int PACK_THREADS = 256;
 
-// One stage's operand words as loaded (raw) with in-matrix flags; they are
-// converted after the stage's MFMAs so that the loads' latency overlaps them.
-struct F64Regs {
-    uint32_t a[8];
-    uint32_t b[8];
-    uint32_t oka, okb; // bit q: element q lies inside the matrix
+// Thread q packs row r = q % rows_pad, K columns 16*kc .. +15, kc = q /
+// rows_pad; 16 consecutive rows write 256 contiguous bytes per 16-byte word.
+__device__ __forceinline__ void pack_one(const SliceJob &J, int64_t q)
+{
+    const int nchunk = J.KP / F64_BK;
+    if (q >= (int64_t)J.rows_pad * nchunk) return;
+    const int r = (int)(q % J.rows_pad);
+    const int kc = (int)(q / J.rows_pad);
+    const int k0 = kc * F64_BK;
+    const uint32_t half = (J.p - 1) / 2;
+    const bool row_ok = r < J.rows;
+
+    double v[F64_BK];
+#pragma unroll
+    for (int e = 0; e < F64_BK; ++e) {
+        const bool ok = row_ok && (k0 + e) < J.K;
+        const uint32_t *src = (const uint32_t *)J.X +
+                              (J.trans ? (int64_t)(k0 + e) * J.ldx + r : (int64_t)r * J.ldx + k0 + e);
+        const uint32_t u = ok ? *src : 0u;
+        const int32_t c = J.in_mode == IN_SIGNED ? (int32_t)u : center(u, J.p, half);
+        v[e] = ok ? (double)c : 0.0;
+    }
+    double *dst = (double *)J.D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * F64_BK +
+                  (int64_t)((r % J.RT) >> 4) * 256 + (r & 15) * 2;
+#pragma unroll
+    for (int c = 0; c < F64_BK / 2; ++c) *(v2d *)(dst + c * 32) = v2d{v[2 * c], v[2 * c + 1]};
+}
+
+__global__ __launch_bounds__(PACK_THREADS) void k_pack_f64(SliceJob J)
+{
+    pack_one(J, (int64_t)blockIdx.x * PACK_THREADS + threadIdx.x);
+}
+
+__global__ __launch_bounds__(PACK_THREADS) void k_pack_f64_batched(
+    const SliceJob *__restrict__ jobs, int njobs)
+{
+    int lo = 0, hi = njobs - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_start <= b) lo = mid; else hi = mid - 1;
+    }
+    const SliceJob J = jobs[lo];
+    pack_one(J, (int64_t)(b - J.block_start) * PACK_THREADS + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM on packed doubles
+// ---------------------------------------------------------------------------
+template <int WGM, int WGN, int NST>
+struct F64Cfg {
+    static constexpr int BM = 64 * WGM;
+    static constexpr int BN = 64 * WGN;
+    static constexpr int NW = WGM * WGN;
+    static constexpr int A_BYTES = BM * F64_BK * 8;
+    static constexpr int B_BYTES = BN * F64_BK * 8;
+    static constexpr int STAGE = A_BYTES + B_BYTES;
+    static constexpr int CHUNKS = STAGE / 1024; // 1 KB per wave load
+    static constexpr int PER_WAVE = (CHUNKS + NW - 1) / NW;
+    static constexpr int BYTES = NST * STAGE;
+    static_assert(NST >= 2, "ring needs two slots");
+    static_assert(BYTES <= LDS_LIMIT, "ring exceeds LDS");
 };
 
-// Operand element (clamped address, always in bounds) -> centered value, or
-// 0 outside the matrix.  The loads are unconditional so that all of a
-// stage's loads are in flight together.
-template <int MODE>
-__device__ __forceinline__ int32_t cvt(uint32_t raw, bool ok, uint32_t p, uint32_t half)
+template <class C>
+__device__ __forceinline__ int issue_stage(const F64Job &J, int tm, int tn, int kt,
+                                           char *lds_stage, int wave, int lane)
 {
-    const int32_t v = MODE == IN_SIGNED ? (int32_t)raw : center(raw, p, half);
-    return ok ? v : 0;
-}
-
-template <int TA, int TB, int MODE>
-__device__ __forceinline__ void load_stage(const F64Job &J, int m0, int n0,
-                                           int k0, int tid, uint32_t half,
-                                           F64Regs &R)
-{
-    const uint32_t *A = (const uint32_t *)J.A;
-    const uint32_t *B = (const uint32_t *)J.B;
-    const int km = J.k - 1, mm = J.m - 1, nm = J.n - 1;
-    uint32_t oka = 0, okb = 0;
-    if (!TA) { // A is m x k: lanes run along k
-        const int kg = k0 + (tid & 15);
-        const int kc = kg < km ? kg : km;
-        const int r0 = m0 + (tid >> 4);
+    const char *Abase = (const char *)(J.Ad + (int64_t)tm * C::BM * J.KP + (int64_t)kt * C::BM * F64_BK);
+    const char *Bbase = (const char *)(J.Bd + (int64_t)tn * C::BN * J.KP + (int64_t)kt * C::BN * F64_BK);
+    int issued = 0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int r = r0 + 16 * q;
-            R.a[q] = A[(int64_t)(r < mm ? r : mm) * J.lda + kc];
-            oka |= (uint32_t)(r < J.m && kg < J.k) << q;
-        }
-    } else { // A is k x m: lanes run along m
-        const int r = m0 + (tid & 127), kq = k0 + (tid >> 7);
-        const int rc = r < mm ? r : mm;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int kg = kq + 2 * q;
-            R.a[q] = A[(int64_t)(kg < km ? kg : km) * J.lda + rc];
-            oka |= (uint32_t)(r < J.m && kg < J.k) << q;
+    for (int i = 0; i < C::PER_WAVE; ++i) {
+        const int c = wave + i * C::NW;
+        if (C::CHUNKS % C::NW == 0 || c < C::CHUNKS) {
+            const int off = c * 1024;
+            const char *src = off < C::A_BYTES ? Abase + off : Bbase + (off - C::A_BYTES);
+            __builtin_amdgcn_global_load_lds((const void *)(src + lane * 16),
+                                             (lds_ptr)(lds_stage + off), 16, 0, 0);
+            ++issued;
         }
     }
-    if (!TB) { // B is k x n: lanes run along n
-        const int c = n0 + (tid & 127), kq = k0 + (tid >> 7);
-        const int cc = c < nm ? c : nm;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int kg = kq + 2 * q;
-            R.b[q] = B[(int64_t)(kg < km ? kg : km) * J.ldb + cc];
-            okb |= (uint32_t)(c < J.n && kg < J.k) << q;
-        }
-    } else { // B is n x k: lanes run along k
-        const int kg = k0 + (tid & 15);
-        const int kc = kg < km ? kg : km;
-        const int c0 = n0 + (tid >> 4);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = c0 + 16 * q;
-            R.b[q] = B[(int64_t)(c < nm ? c : nm) * J.ldb + kc];
-            okb |= (uint32_t)(c < J.n && kg < J.k) << q;
-        }
-    }
-    R.oka = oka;
-    R.okb = okb;
-}
-
-template <int TA, int TB, int MODE>
-__device__ __forceinline__ void store_stage(int tid, const F64Regs &R, uint32_t p,
-                                            uint32_t half, double (*sA)[LDP],
-                                            double (*sB)[LDP])
-{
-#define VA(q) (double)cvt<MODE>(R.a[q], (R.oka >> (q)) & 1u, p, half)
-#define VB(q) (double)cvt<MODE>(R.b[q], (R.okb >> (q)) & 1u, p, half)
-    if (!TA) {
-        const int kk = tid & 15, r0 = tid >> 4;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) sA[kk][r0 + 16 * q] = VA(q);
-    } else {
-        const int r = tid & 127, kq = tid >> 7;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) sA[kq + 2 * q][r] = VA(q);
-    }
-    if (!TB) {
-        const int c = tid & 127, kq = tid >> 7;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) sB[kq + 2 * q][c] = VB(q);
-    } else {
-        const int kk = tid & 15, c0 = tid >> 4;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) sB[kk][c0 + 16 * q] = VB(q);
-    }
-#undef VA
-#undef VB
+    return issued;
 }
 
 __device__ __forceinline__ void fold(v4d (&acc)[4][4], double pd, double pinv)
@@ -133,17 +138,16 @@ __device__ __forceinline__ void fold(v4d (&acc)[4][4], double pd, double pinv)
             }
 }
 
-// One 128 x 128 output tile.  smem: 2 stages x (A, B) x 16 x LDP doubles.
-template <int TA, int TB, int MODE>
-__device__ void f64_tile(const F64Job &J, int tm, int tn, double *smem)
+// One output tile.  FINE: reduce after every 4-product matrix-core step
+// (fewer than 16 products fit below 2^53), else every fold_stages stages.
+// SPLIT: schedule for two waves per SIMD (see the loop).
+template <int WGM, int WGN, int NST, bool SPLIT, bool FINE>
+__device__ void f64_tile(const F64Job &J, int tm, int tn, char *smem)
 {
+    using C = F64Cfg<WGM, WGN, NST>;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int m0 = tm * F64_BM, n0 = tn * F64_BN;
-    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
-    const uint32_t half = (J.p - 1) / 2;
-    double(*sA)[F64_BK][LDP] = (double(*)[F64_BK][LDP])smem;
-    double(*sB)[F64_BK][LDP] = (double(*)[F64_BK][LDP])(smem + 2 * F64_BK * LDP);
+    const int wm0 = (wave / WGN) * 64, wn0 = (wave % WGN) * 64;
 
     v4d acc[4][4];
 #pragma unroll
@@ -151,104 +155,133 @@ __device__ void f64_tile(const F64Job &J, int tm, int tn, double *smem)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    const int nk = (J.k + F64_BK - 1) / F64_BK;
-    F64Regs R;
-    load_stage<TA, TB, MODE>(J, m0, n0, 0, tid, half, R);
-    store_stage<TA, TB, MODE>(tid, R, J.p, half, sA[0], sB[0]);
-    __syncthreads();
+    const int nk = J.KP / F64_BK;
+    int per_stage = 0;
+#pragma unroll
+    for (int st = 0; st < NST - 1; ++st)
+        per_stage = issue_stage<C>(J, tm, tn, st < nk ? st : nk - 1, smem + st * C::STAGE, wave,
+                                   lane);
 
-    int cnt = 0;
+    // Fragment offsets inside a stage: in 16-row block b (2048 bytes), lane
+    // l reads the 16-byte word of row l%16 holding K values 4(l/16) + 2h, +1.
+    const int frag = (2 * (lane >> 4)) * 256 + (lane & 15) * 16;
+    int since = 0;
     for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) load_stage<TA, TB, MODE>(J, m0, n0, (kt + 1) * F64_BK, tid, half, R);
+        // Stage kt has landed once at most the NST-2 later stages' loads of
+        // this wave are outstanding; after the barrier every wave's part is
+        // in LDS, and the slot of stage kt-1 is free for stage kt+NST-1.
+        wait_vm((NST - 2) * per_stage);
+        ring_barrier();
+        const char *cur = smem + (kt % NST) * C::STAGE;
+        v2d a[2][4], b[2][4];
 #pragma unroll
-        for (int ks = 0; ks < F64_BK / 4; ++ks) {
-            const int kr = ks * 4 + (lane >> 4);
-            double a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = sA[buf][kr][wm0 + i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = sB[buf][kr][wn0 + j * 16 + (lane & 15)];
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
+                a[h][i] = *(const v2d *)(cur + ((wm0 >> 4) + i) * 2048 + frag + h * 256);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-            if (++cnt == J.fold_every) {
+            for (int j = 0; j < 4; ++j)
+                b[h][j] = *(const v2d *)(cur + C::A_BYTES + ((wn0 >> 4) + j) * 2048 + frag + h * 256);
+        }
+        const int nxt = kt + NST - 1;
+        issue_stage<C>(J, tm, tn, nxt < nk ? nxt : nk - 1, smem + (nxt % NST) * C::STAGE, wave,
+                       lane);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][i][s], b[h][j][s],
+                                                                         acc[i][j], 0, 0, 0);
+                if (FINE) fold(acc, J.pd, J.pinv);
+            }
+        if (!FINE) {
+            // Schedule: the next stage's loads spread between the
+            // matrix-core instructions.  With one wave per SIMD all fragment
+            // reads go first; with two, the second half's reads wait for the
+            // first half's matrix-core work (the other wave hides their
+            // latency) so that fewer fragment registers are live.
+            constexpr int NMF = 64, NLD = C::PER_WAVE;
+            if (SPLIT) {
+                constexpr int GAP = (NMF / 2) / (NLD + 1);
+                __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+                for (int q = 0; q < NLD; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, GAP, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF / 2 - NLD * GAP, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF / 2, 0);
+            } else {
+                constexpr int GAP = NMF / (NLD + 1);
+                __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+#pragma unroll
+                for (int q = 0; q < NLD; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, GAP, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF - NLD * GAP, 0);
+            }
+            if (++since == J.fold_stages) {
                 fold(acc, J.pd, J.pinv);
-                cnt = 0;
+                since = 0;
             }
         }
-        if (kt + 1 < nk) store_stage<TA, TB, MODE>(tid, R, J.p, half, sA[buf ^ 1], sB[buf ^ 1]);
-        __syncthreads();
     }
+    // drain the (dummy) loads still in flight before the ring is left
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // every wave is done with the ring before a persistent workgroup reuses it
+    __syncthreads();
 
     // Epilogue: in each 16 x 16 block the lane holds column lane%16 of rows
     // lane/16 + 4r, r = 0..3 (v_mfma_f64_16x16x4 result layout).
+    const int m0 = tm * C::BM, n0 = tn * C::BN;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm0 + i * 16 + (lane >> 4) + 4 * r;
-                const int col = n0 + wn0 + j * 16 + (lane & 15);
-                if (row < J.m && col < J.n) {
+                const int gr = m0 + wm0 + i * 16 + (lane >> 4) + 4 * r;
+                const int gc = n0 + wn0 + j * 16 + (lane & 15);
+                if (gr < J.m && gc < J.n) {
                     const uint32_t v = canon_f64(acc[i][j][r], J.pd, J.pinv, J.p);
                     uint32_t out = mulmod(J.alpha, v, J.p, J.pinv);
-                    uint32_t *cp = J.C + (int64_t)row * J.ldc + col;
+                    uint32_t *cp = J.C + (int64_t)gr * J.ldc + gc;
                     if (J.beta) out = addmod(out, mulmod(J.beta, *cp, J.p, J.pinv), J.p);
                     *cp = out;
                 }
             }
 }
 
-constexpr size_t F64_SMEM = sizeof(double) * 2 * 2 * F64_BK * LDP;
-
-template <int TA, int TB, int MODE>
-__global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64(F64Job J)
+// FINE (reduction after every matrix-core step) is a separate instantiation
+// chosen on the host: its extra live values would make the common kernel
+// spill.
+template <int WGM, int WGN, int NST, int WPE, bool FINE>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
+                          amdgpu_waves_per_eu(WPE, WPE)))
+void k_fgemm_f64(F64Job J)
 {
-    __shared__ double smem[F64_SMEM / sizeof(double)];
+    __shared__ __attribute__((aligned(1024))) char smem[F64Cfg<WGM, WGN, NST>::BYTES];
     const int G = J.tiles_m * J.tiles_n;
     const int t = xcd_remap(blockIdx.x, G);
     int tm, tn;
-    grouped_tile<8>(t, J.tiles_m, J.tiles_n, &tm, &tn);
-    f64_tile<TA, TB, MODE>(J, tm, tn, smem);
+    grouped_tile_rt(t, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
+    f64_tile<WGM, WGN, NST, (WPE > 1), FINE>(J, tm, tn, smem);
 }
 
-// Runtime flags -> instantiation.
-template <template <int, int, int> class K, class... Args>
-hipError_t f64_dispatch(int ta, int tb, int mode, Args... args)
+// Every job of the table must have fold_stages == 0 iff FINE.
+template <int WGM, int WGN, int NST, int WPE, bool FINE>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
+                          amdgpu_waves_per_eu(WPE, WPE)))
+void k_fgemm_f64_batched(const F64Job *__restrict__ jobs, int njobs, int total, int persistent,
+                         unsigned *ctr)
 {
-    const int key = ta * 4 + tb * 2 + mode;
-    switch (key) {
-    case 0: return K<0, 0, 0>::go(args...);
-    case 1: return K<0, 0, 1>::go(args...);
-    case 2: return K<0, 1, 0>::go(args...);
-    case 3: return K<0, 1, 1>::go(args...);
-    case 4: return K<1, 0, 0>::go(args...);
-    case 5: return K<1, 0, 1>::go(args...);
-    case 6: return K<1, 1, 0>::go(args...);
-    default: return K<1, 1, 1>::go(args...);
-    }
-}
-
-__device__ __forceinline__ int find_job_f64(const F64Job *jobs, int njobs, int g)
-{
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile_start <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-template <int TA, int TB, int MODE>
-__global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64_batched(
-    const F64Job *__restrict__ jobs, int njobs, int total, int persistent,
-    unsigned *ctr)
-{
-    __shared__ double smem[F64_SMEM / sizeof(double)];
+    __shared__ __attribute__((aligned(1024))) char smem[F64Cfg<WGM, WGN, NST>::BYTES];
     __shared__ int s_tile;
     int g = persistent ? 0 : (int)blockIdx.x;
     for (;;) {
@@ -259,12 +292,15 @@ __global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64_batched(
             __syncthreads();
         }
         if (g >= total) break;
-        const int j = find_job_f64(jobs, njobs, g);
-        const F64Job J = jobs[j];
-        const int local = g - J.tile_start;
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_start <= g) lo = mid; else hi = mid - 1;
+        }
+        const F64Job J = jobs[lo];
         int tm, tn;
-        grouped_tile<8>(local, J.tiles_m, J.tiles_n, &tm, &tn);
-        f64_tile<TA, TB, MODE>(J, tm, tn, smem);
+        grouped_tile_rt(g - J.tile_start, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
+        f64_tile<WGM, WGN, NST, (WPE > 1), FINE>(J, tm, tn, smem);
         if (!persistent) break;
     }
     if (persistent && threadIdx.x == 0) {
@@ -279,49 +315,97 @@ __global__ __launch_bounds__(F64_THREADS) void k_fgemm_f64_batched(
     }
 }
 
-template <int TA, int TB, int MODE>
-struct SingleF64 {
-    static hipError_t go(const F64Job &job, hipStream_t st)
-    {
-        const int G = job.tiles_m * job.tiles_n;
-        hipLaunchKernelGGL((k_fgemm_f64<TA, TB, MODE>), dim3(G), dim3(F64_THREADS), 0, st, job);
-        return hipGetLastError();
-    }
-};
-
-template <int TA, int TB, int MODE>
-struct BatchedF64 {
-    static hipError_t go(const F64Job *jobs, int njobs, int total, int persistent,
-                         unsigned *ctr, int grid, hipStream_t st)
-    {
-        hipLaunchKernelGGL((k_fgemm_f64_batched<TA, TB, MODE>), dim3(grid), dim3(F64_THREADS),
-                           0, st, jobs, njobs, total, persistent, ctr);
-        return hipGetLastError();
-    }
-};
-
-} // namespace
-
-hipError_t launch_f64(const F64Job &job, hipStream_t st)
+template <int WGM, int WGN, int NST, int WPE>
+hipError_t run_single(const F64Job &J, hipStream_t st)
 {
-    return f64_dispatch<SingleF64>(job.transA, job.transB, job.in_mode, job, st);
+    const int G = J.tiles_m * J.tiles_n;
+    if (J.fold_stages > 0)
+        hipLaunchKernelGGL((k_fgemm_f64<WGM, WGN, NST, WPE, false>), dim3(G),
+                           dim3(64 * WGM * WGN), 0, st, J);
+    else
+        hipLaunchKernelGGL((k_fgemm_f64<WGM, WGN, NST, WPE, true>), dim3(G),
+                           dim3(64 * WGM * WGN), 0, st, J);
+    return hipGetLastError();
 }
 
-// A batched table must share transposes and input mode (the first job's).
-hipError_t launch_f64_batched(const F64Job *dev_jobs, int njobs, int total_tiles,
-                              int persistent, unsigned *ctr, int ta, int tb, int mode,
-                              hipStream_t st)
+template <int WGM, int WGN, int NST, int WPE>
+hipError_t run_batched(const F64Job *jobs, int njobs, int total, int persistent, unsigned *ctr,
+                       int fine, hipStream_t st)
 {
-    int grid = total_tiles;
+    int grid = total;
     if (persistent) {
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = cus * 2 < total_tiles ? cus * 2 : total_tiles;
+        // workgroups resident per CU: WPE waves on each of the 4 SIMDs
+        const int per_cu = (4 * WPE) / (WGM * WGN) > 0 ? (4 * WPE) / (WGM * WGN) : 1;
+        grid = cus * per_cu < total ? cus * per_cu : total;
         if (grid < 1) grid = 1;
     }
-    return f64_dispatch<BatchedF64>(ta, tb, mode, (const F64Job *)dev_jobs, njobs, total_tiles,
-                                    persistent, ctr, grid, st);
+    if (fine)
+        hipLaunchKernelGGL((k_fgemm_f64_batched<WGM, WGN, NST, WPE, true>), dim3(grid),
+                           dim3(64 * WGM * WGN), 0, st, jobs, njobs, total, persistent, ctr);
+    else
+        hipLaunchKernelGGL((k_fgemm_f64_batched<WGM, WGN, NST, WPE, false>), dim3(grid),
+                           dim3(64 * WGM * WGN), 0, st, jobs, njobs, total, persistent, ctr);
+    return hipGetLastError();
+}
+
+const F64Tile kTiles[] = {
+#define FF_ROW(id, WGM, WGN, NST, WPE, GM) {id, WGM, WGN, NST, WPE, GM},
+    FF_F64_TILES(FF_ROW)
+#undef FF_ROW
+};
+
+} // namespace
+
+int f64_tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
+const F64Tile &f64_tile(int id) { return kTiles[id]; }
+int f64_default_tile() { return 1; }
+
+hipError_t launch_f64(int tile, const F64Job &J, hipStream_t st)
+{
+    switch (tile) {
+#define FF_CASE(id, WGM, WGN, NST, WPE, GM) \
+    case id: return run_single<WGM, WGN, NST, WPE>(J, st);
+        FF_F64_TILES(FF_CASE)
+#undef FF_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_f64_batched(int tile, const F64Job *jobs, int njobs, int total, int persistent,
+                              unsigned *ctr, int fine, hipStream_t st)
+{
+    switch (tile) {
+#define FF_CASE(id, WGM, WGN, NST, WPE, GM) \
+    case id: return run_batched<WGM, WGN, NST, WPE>(jobs, njobs, total, persistent, ctr, fine, st);
+        FF_F64_TILES(FF_CASE)
+#undef FF_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack_f64(const SliceJob &J, hipStream_t st)
+{
+    const int64_t total = (int64_t)J.rows_pad * (J.KP / F64_BK);
+    const int64_t grid = (total + PACK_THREADS - 1) / PACK_THREADS;
+    hipLaunchKernelGGL(k_pack_f64, dim3((unsigned)grid), dim3(PACK_THREADS), 0, st, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_f64_batched(const SliceJob *dev_jobs, int njobs, int total_blocks,
+                                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_f64_batched, dim3(total_blocks), dim3(PACK_THREADS), 0, st,
+                       dev_jobs, njobs);
+    return hipGetLastError();
+}
+
+int pack_blocks(const SliceJob &J)
+{
+    const int64_t total = (int64_t)J.rows_pad * (J.KP / F64_BK);
+    return (int)((total + PACK_THREADS - 1) / PACK_THREADS);
 }
 
 } // namespace ff

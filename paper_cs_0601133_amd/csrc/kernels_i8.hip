@@ -18,12 +18,12 @@
 // matrix-core operands are read back.
 #include "ff_device.h"
 #include "ff_internal.h"
+#include "ff_ring.h"
 
 namespace ff {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
-typedef __attribute__((address_space(3))) void *lds_ptr;
 
 namespace {
 
@@ -98,7 +98,6 @@ __global__ __launch_bounds__(SLICE_THREADS) void k_slice_batched(
 // ---------------------------------------------------------------------------
 // GEMM on digit planes
 // ---------------------------------------------------------------------------
-constexpr int LDS_LIMIT = 160 * 1024 - 1024; // leave room for small shared variables
 
 
 
@@ -129,33 +128,6 @@ struct Ring {
     static constexpr int NST = FIT > 6 ? 6 : (FIT < 2 ? 2 : FIT);
     static constexpr int BYTES = NST * STAGE;
 };
-
-// s_waitcnt needs an immediate: wait until at most n vector memory
-// operations of this wave are outstanding.
-__device__ __forceinline__ void wait_vm(int n)
-{
-    switch (n) {
-#define FF_W(k) case k: asm volatile("s_waitcnt vmcnt(" #k ")" ::: "memory"); break;
-        FF_W(0) FF_W(1) FF_W(2) FF_W(3) FF_W(4) FF_W(5) FF_W(6) FF_W(7)
-        FF_W(8) FF_W(9) FF_W(10) FF_W(11) FF_W(12) FF_W(13) FF_W(14) FF_W(15)
-#undef FF_W
-    default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-    }
-}
-
-// Workgroup barrier without the memory fence of __syncthreads (which would
-// make every wave drain all of its outstanding global loads, i.e. every
-// stage in flight).  Ordering is explicit instead: each wave waits for its
-// own loads of the stage with wait_vm before the barrier, and every read of
-// a ring slot feeds a matrix-core instruction issued before the barrier, so
-// the slot is free when the barrier completes.  The empty asm statements
-// keep the compiler from moving memory accesses across it.
-__device__ __forceinline__ void ring_barrier()
-{
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
 // Issue the direct-to-LDS loads of stage kt; returns how many this wave
 // issued.

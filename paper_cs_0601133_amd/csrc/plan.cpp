@@ -135,6 +135,17 @@ int crossover_w()
 
 } // namespace
 
+// FF_F64_TILE (an id) overrides the default FP64 configuration.
+int choose_f64_tile()
+{
+    const char *e = std::getenv("FF_F64_TILE");
+    if (e && *e) {
+        const int id = std::atoi(e);
+        if (id >= 0 && id < f64_tile_count()) return id;
+    }
+    return f64_default_tile();
+}
+
 int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
               Plan *pl)
 {
@@ -195,6 +206,7 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         P.hi = reduce ? wid_r.hi : wid_d.hi;
         P.max_prod = reduce ? mp_r : mp_d;
         P.kblock = kb;
+        P.tile = choose_f64_tile();
     } else {
         int best_s = 0, best_bits = 0, best_reduce = 0;
         for (int reduce = 0; reduce <= (L > 0 ? 1 : 0); ++reduce) {
@@ -239,8 +251,14 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         const int64_t np = round_up(std::max<int64_t>(nl, 1), t.bn());
         ws += nleaf * P.slices * (mp + np) * KP;
         if (L > 0) ws += nleaf * ml * nl * 4 + 256;
-    } else if (L > 0) {
-        ws += nleaf * (ml * kl + kl * nl) * 4 + nleaf * ml * nl * 4 + 256;
+    } else {
+        // packed double operands of every leaf
+        const F64Tile &t = f64_tile(P.tile);
+        const int64_t KP = round_up(std::max<int64_t>(kl, 1), F64_BK);
+        const int64_t mp = round_up(std::max<int64_t>(ml, 1), t.bm());
+        const int64_t np = round_up(std::max<int64_t>(nl, 1), t.bn());
+        ws += nleaf * (mp + np) * KP * 8;
+        if (L > 0) ws += nleaf * (ml * kl + kl * nl) * 4 + nleaf * ml * nl * 4 + 256;
     }
     if (L > 0) ws += nleaf * 256 + 4096; // job tables
     P.ws_bytes = ws;

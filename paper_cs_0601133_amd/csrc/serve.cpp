@@ -12,8 +12,8 @@
 //   * records latency (submit to observed completion) per request.
 // The footprint of a request is the HBM it touches while in flight: its
 // operands and C (4(mk + kn + mn) bytes) plus its share of the batch
-// workspace (digit planes, tables), which comes from a device arena of the
-// budget's size owned by the server.
+// workspace (digit planes or packed doubles, tables), which comes from a
+// device arena of the budget's size owned by the server.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -149,6 +149,10 @@ static int64_t footprint_of(const IJob &j)
         const int64_t KP = round_up(std::max<int64_t>(j.k, 1), I8_BK);
         f += (int64_t)j.S * (round_up(j.m, std::max(t.bm(), 256)) +
                              round_up(j.n, std::max(t.bn(), 256))) * KP;
+    } else if (j.path == FF_PATH_FP64) {
+        // packed double operands (row tiles of at most 256)
+        const int64_t KP = round_up(std::max<int64_t>(j.k, 1), F64_BK);
+        f += (round_up(j.m, 256) + round_up(j.n, 256)) * KP * 8;
     }
     return align256(f);
 }
@@ -216,7 +220,7 @@ bool Server::admit_locked()
         f.slot = slot;
         f.ids = pick;
         f.footprint = fp;
-        int tile = path == FF_PATH_INT8 ? i8_default_tile(Smax) : -1;
+        int tile = path == FF_PATH_INT8 ? i8_default_tile(Smax) : choose_f64_tile();
         int rc = prep_batch(jobs, path, tile, &f.prep);
         if (rc == FF_OK && !arena.alloc(std::max<int64_t>(f.prep.ws_bytes, 256), &f.arena_off)) {
             // fragmented arena: put the requests back (in order) and wait for
