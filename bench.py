@@ -7,7 +7,8 @@ path with 4 signed 7-bit digits: slicing of A and B into digit planes, 16
 digit-pair products on INT8 matrix cores with int32 sums, and the epilogue
 that recombines the digits modulo p and applies alpha and beta.  The metric
 is 2mnk / t (Gop/s); the same workload is also timed on the FP64
-matrix-core path (K-block 512) and with 8-bit digits (3 slices).
+matrix-core path (operands packed as centered doubles, reduction every 512
+products) and with 8-bit digits (3 slices).
 
 The JSON line also carries the roofline of the dominant kernel (the INT8
 digit GEMM, timed with HIP events around its launches), the CPU oracle timed
@@ -36,7 +37,10 @@ M = N = K = 4096
 P = 8388593
 ALPHA, BETA = 3, 5
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fgemm_i8_S4_n4096_traffic.txt")
-I8_SOURCE = os.path.join(ROOT, "paper_cs_0601133_amd", "csrc", "kernels_i8.hip")
+# sources the INT8 digit GEMM is compiled from (the traffic figures hold
+# only while these are unchanged)
+I8_SOURCES = [os.path.join(ROOT, "paper_cs_0601133_amd", "csrc", f)
+              for f in ("kernels_i8.hip", "ff_ring.h", "ff_device.h")]
 
 
 def parse():
@@ -101,10 +105,13 @@ def cpu_baseline(A, B, C, seconds):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    # probe with one row per thread (the oracle parallelises over rows), then
+    # size the sample to about `seconds` of work in whole rounds of rows
+    probe = max(4, threads)
     t = time.perf_counter()
-    oracle.fgemm(P, A[:4], B, C[:4], ALPHA, BETA)
+    oracle.fgemm(P, A[:probe], B, C[:probe], ALPHA, BETA)
     dt = max(time.perf_counter() - t, 1e-3)
-    rows = int(max(4, min(M, 4 * seconds / dt)))
+    rows = int(max(probe, min(M, probe * max(1, round(seconds / dt)))))
     t = time.perf_counter()
     oracle.fgemm(P, A[:rows], B, C[:rows], ALPHA, BETA)
     dt = time.perf_counter() - t
@@ -112,6 +119,13 @@ def cpu_baseline(A, B, C, seconds):
             "kind": "oracle",
             "sample": f"{rows} full rows of the 4096 x 4096 x 4096 product mod 8388593 "
                       f"({rows * N * K:.3g} multiply-adds, {dt:.1f} s), scaled to Gop/s"}
+
+
+def i8_source_sha256():
+    h = hashlib.sha256()
+    for f in I8_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
@@ -123,7 +137,7 @@ def measured_traffic():
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        sha = hashlib.sha256(open(I8_SOURCE, "rb").read()).hexdigest()
+        sha = i8_source_sha256()
         if kv.get("source_sha256") != sha:
             return None
         return float(kv["hbm_bytes_per_launch"])
