@@ -97,7 +97,29 @@ def test_batch_mixed_moduli_transposes_and_quick_jobs():
             assert np.array_equal(from_dev(dC), want), (path, p)
 
 
-def test_batch_graph_replays():
+def test_fp64_batch_mixes_reduction_schedules():
+    # FP64 jobs reduced every few K stages and jobs reduced after every
+    # matrix-core step (p above about 4.7e7) run as two persistent launches
+    specs = [(65521, 96, 80, 300, False, False), (94906249, 70, 130, 257, True, False),
+             (8388593, 129, 65, 1100, False, True), (47499979, 33, 200, 64, True, True),
+             (33554393, 256, 256, 640, False, False), (94906249, 1, 1, 1, False, False)]
+    items, abi = [], []
+    for i, (p, m, n, k, tA, tB) in enumerate(specs):
+        Ap = synth.residues(synth.seed_for(60 + i, 1), (k, m) if tA else (m, k), p)
+        Bp = synth.residues(synth.seed_for(60 + i, 2), (n, k) if tB else (k, n), p)
+        Cp = synth.residues(synth.seed_for(60 + i, 3), (m, n), p)
+        dA, dB, dC = to_dev(Ap), to_dev(Bp), to_dev(Cp)
+        items.append((p, Ap, Bp, Cp, tA, tB, dA, dB, dC))
+        abi.append(ff.job(p, dA, dB, dC, 5, 7, tA, tB))
+    rc = ff.ff_fgemm_batched(abi, ff.make_opts(path=ff.FF_PATH_FP64))
+    assert rc == ff.FF_OK, ff.ff_last_error()
+    for (p, Ap, Bp, Cp, tA, tB, dA, dB, dC) in items:
+        want = oracle.fgemm(p, Ap, Bp, Cp, 5, 7, tA, tB)
+        assert np.array_equal(from_dev(dC), want), p
+
+
+@pytest.mark.parametrize("path", [ff.FF_PATH_INT8, ff.FF_PATH_FP64], ids=["int8", "fp64"])
+def test_batch_graph_replays(path):
     import torch
     A, B, jobs = multimodular(192, [64, 128, 192], 6, 41)
     dev, abi, keep = [], [], []
@@ -109,7 +131,7 @@ def test_batch_graph_replays():
         dev.append((p, Ap, Bp, dC))
         abi.append(ff.job(p, dA, dB, dC, 3, 0))
     wants = [oracle.fgemm(p, Ap, Bp, None, 3, 0) for (p, Ap, Bp, _) in dev]
-    g = ff.ff_batch_graph_create(abi, ff.make_opts(path=ff.FF_PATH_INT8))
+    g = ff.ff_batch_graph_create(abi, ff.make_opts(path=path))
     try:
         stream = torch.cuda.current_stream()
         for replay in range(4):

@@ -110,6 +110,22 @@ def test_fp64_folds_every_kblock():
     assert np.array_equal(got, oracle.fgemm(p, A, B, C, 3, 5))
 
 
+@pytest.mark.parametrize("p", [33554393, 47499979, 94906249])
+def test_fp64_large_moduli_reduction_schedule(p):
+    # K-blocks 32 (a reduction every two K stages), 15 and 4 (a reduction
+    # after every matrix-core step): random operands, then every product at
+    # the largest magnitude with one sign, where a late reduction overflows
+    # 2^53 and loses exactness
+    A, B, C = inputs(p, 130, 150, 700, 13)
+    got = run(p, A, B, C, 3, 5, path=FP64)
+    assert np.array_equal(got, oracle.fgemm(p, A, B, C, 3, 5))
+    m, n, k = 64, 80, 1000
+    A = np.full((m, k), p // 2, np.uint32)          # centered (p - 1)/2
+    B = np.full((k, n), (p + 1) // 2, np.uint32)    # centered -(p - 1)/2
+    got = run(p, A, B, np.zeros((m, n), np.uint32), 1, 0, path=FP64)
+    assert np.array_equal(got, oracle.fgemm(p, A, B, None, 1, 0))
+
+
 def test_int8_k_split_beyond_int32_block():
     # p = 251 direct plane: one int32 pass is exact up to k = 137438, so
     # k = 140000 takes two passes chained with beta = 1
