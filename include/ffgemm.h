@@ -189,14 +189,19 @@ int ff_server_destroy(void *server);
 int ff_autotune(int slices, int64_t m, int64_t n, int64_t k, int *best_tile,
                 double *best_ms);
 
-/* Kernel timing for measurement.  While enabled, every launch of the
- * matrix-core kernels (FP64 and INT8 fgemm, single or batched) is bracketed
- * by a HIP event pair recorded on the stream it is launched on, and so is
- * every digit-slicing launch.  ff_profile_read synchronises those events
- * and returns the summed durations (ms) and launch counts since the last
- * enable or read, then clears them.  Not thread-safe against concurrent
- * fgemm calls; meant for benchmarks. */
-int ff_profile_enable(int on);
+/* Kernel timing for measurement.  ff_profile_enable(mask) clears what was
+ * recorded and selects which launches get bracketed by a HIP event pair on
+ * the stream they are launched on: FF_PROFILE_GEMM the matrix-core kernels
+ * (FP64 and INT8 fgemm, single or batched), FF_PROFILE_PREP the operand
+ * passes (digit slicing, FP64 packing); 0 disables.  Each event pair adds a
+ * few microseconds between kernels, so a timing run brackets only what it
+ * reports.  ff_profile_read synchronises those events and returns the
+ * summed durations (ms) and launch counts since the last enable or read,
+ * then clears them.  Not thread-safe against concurrent fgemm calls; meant
+ * for benchmarks. */
+#define FF_PROFILE_GEMM 1
+#define FF_PROFILE_PREP 2
+int ff_profile_enable(int mask);
 int ff_profile_read(double *gemm_ms, int64_t *gemm_launches,
                     double *slice_ms, int64_t *slice_launches);
 

@@ -19,6 +19,7 @@
 //     canonical and applies alpha and beta modulo p.
 #include "ff_device.h"
 #include "ff_internal.h"
+#include "ff_operand.h"
 #include "ff_ring.h"
 
 namespace ff {
@@ -38,44 +39,34 @@ namespace {
 // ---------------------------------------------------------------------------
 // Packing: operand -> centered doubles
 // ---------------------------------------------------------------------------
-constexpr int PACK_THREADS = 256;
-
-// Thread q packs row r = q % rows_pad, K columns 16*kc .. +15, kc = q /
-// rows_pad; 16 consecutive rows write 256 contiguous bytes per 16-byte word.
-__device__ __forceinline__ void pack_one(const SliceJob &J, int64_t q)
+// The thread's unit (row r, K columns 16*kc .. +15) becomes eight 16-byte
+// words; 16 consecutive rows write 256 contiguous bytes per word.
+__device__ __forceinline__ void pack_block(const SliceJob &J, int b, UnitTile &tile)
 {
-    const int nchunk = J.KP / F64_BK;
-    if (q >= (int64_t)J.rows_pad * nchunk) return;
-    const int r = (int)(q % J.rows_pad);
-    const int kc = (int)(q / J.rows_pad);
-    const int k0 = kc * F64_BK;
+    uint32_t u[16];
+    int r, kc;
+    if (!load_unit(J, b, tile, u, r, kc)) return;
     const uint32_t half = (J.p - 1) / 2;
-    const bool row_ok = r < J.rows;
-
     double v[F64_BK];
 #pragma unroll
-    for (int e = 0; e < F64_BK; ++e) {
-        const bool ok = row_ok && (k0 + e) < J.K;
-        const uint32_t *src = (const uint32_t *)J.X +
-                              (J.trans ? (int64_t)(k0 + e) * J.ldx + r : (int64_t)r * J.ldx + k0 + e);
-        const uint32_t u = ok ? *src : 0u;
-        const int32_t c = J.in_mode == IN_SIGNED ? (int32_t)u : center(u, J.p, half);
-        v[e] = ok ? (double)c : 0.0;
-    }
+    for (int e = 0; e < F64_BK; ++e)
+        v[e] = (double)(J.in_mode == IN_SIGNED ? (int32_t)u[e] : center(u[e], J.p, half));
     double *dst = (double *)J.D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * F64_BK +
                   (int64_t)((r % J.RT) >> 4) * 256 + (r & 15) * 2;
 #pragma unroll
     for (int c = 0; c < F64_BK / 2; ++c) *(v2d *)(dst + c * 32) = v2d{v[2 * c], v[2 * c + 1]};
 }
 
-__global__ __launch_bounds__(PACK_THREADS) void k_pack_f64(SliceJob J)
+__global__ __launch_bounds__(UNIT_THREADS) void k_pack_f64(SliceJob J)
 {
-    pack_one(J, (int64_t)blockIdx.x * PACK_THREADS + threadIdx.x);
+    __shared__ UnitTile tile;
+    pack_block(J, blockIdx.x, tile);
 }
 
-__global__ __launch_bounds__(PACK_THREADS) void k_pack_f64_batched(
+__global__ __launch_bounds__(UNIT_THREADS) void k_pack_f64_batched(
     const SliceJob *__restrict__ jobs, int njobs)
 {
+    __shared__ UnitTile tile;
     int lo = 0, hi = njobs - 1;
     const int b = blockIdx.x;
     while (lo < hi) {
@@ -83,7 +74,7 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack_f64_batched(
         if (jobs[mid].block_start <= b) lo = mid; else hi = mid - 1;
     }
     const SliceJob J = jobs[lo];
-    pack_one(J, (int64_t)(b - J.block_start) * PACK_THREADS + threadIdx.x);
+    pack_block(J, b - J.block_start, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,24 +379,18 @@ hipError_t launch_f64_batched(int tile, const F64Job *jobs, int njobs, int total
 
 hipError_t launch_pack_f64(const SliceJob &J, hipStream_t st)
 {
-    const int64_t total = (int64_t)J.rows_pad * (J.KP / F64_BK);
-    const int64_t grid = (total + PACK_THREADS - 1) / PACK_THREADS;
-    hipLaunchKernelGGL(k_pack_f64, dim3((unsigned)grid), dim3(PACK_THREADS), 0, st, J);
+    hipLaunchKernelGGL(k_pack_f64, dim3((unsigned)unit_blocks(J)), dim3(UNIT_THREADS), 0, st, J);
     return hipGetLastError();
 }
 
 hipError_t launch_pack_f64_batched(const SliceJob *dev_jobs, int njobs, int total_blocks,
                                    hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pack_f64_batched, dim3(total_blocks), dim3(PACK_THREADS), 0, st,
+    hipLaunchKernelGGL(k_pack_f64_batched, dim3(total_blocks), dim3(UNIT_THREADS), 0, st,
                        dev_jobs, njobs);
     return hipGetLastError();
 }
 
-int pack_blocks(const SliceJob &J)
-{
-    const int64_t total = (int64_t)J.rows_pad * (J.KP / F64_BK);
-    return (int)((total + PACK_THREADS - 1) / PACK_THREADS);
-}
+int pack_blocks(const SliceJob &J) { return unit_blocks(J); }
 
 } // namespace ff

@@ -10,8 +10,9 @@
 // the epilogue reduces each E_t modulo p and forms
 //     C <- sum_t (alpha R^t mod p) (E_t mod p) + beta C   (mod p).
 //
-// Digit planes are stored "packed": for a row tile of RT rows and the K
-// range padded to KP, the 16-byte group (row r, k/16) of digit d sits at
+// Digit planes (written by kernels_slice.hip) are packed: for a row tile of
+// RT rows and the K range padded to KP, the 16-byte group (row r, k/16) of
+// digit d sits at
 //     d*plane + (r/RT)*RT*KP + (k/16)*RT*16 + (r%RT)*16,
 // so the (RT x 64)-byte stage a workgroup needs is one contiguous block and
 // is copied straight into LDS by global_load_lds_dwordx4 in the order the
@@ -26,74 +27,6 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
-
-// ---------------------------------------------------------------------------
-// Slicer: operand -> packed digit planes (zero padded)
-// ---------------------------------------------------------------------------
-constexpr int SLICE_THREADS = 256;
-
-__device__ __forceinline__ void slice_one(const SliceJob &J, int64_t q)
-{
-    const int nchunk = J.KP / 16;
-    if (q >= (int64_t)J.rows_pad * nchunk) return;
-    const int r = (int)(q % J.rows_pad);
-    const int kc = (int)(q / J.rows_pad);
-    const int k0 = kc * 16;
-    const uint32_t half = (J.p - 1) / 2;
-
-    int32_t v[16];
-    const bool row_ok = r < J.rows;
-    if (!J.trans) {
-        const uint32_t *src = (const uint32_t *)J.X + (int64_t)r * J.ldx + k0;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const bool ok = row_ok && (k0 + e) < J.K;
-            const uint32_t u = ok ? src[e] : 0u;
-            v[e] = !ok ? 0 : (J.in_mode == IN_SIGNED ? (int32_t)u : center(u, J.p, half));
-        }
-    } else {
-        const uint32_t *src = (const uint32_t *)J.X + (int64_t)k0 * J.ldx + r;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const bool ok = row_ok && (k0 + e) < J.K;
-            const uint32_t u = ok ? src[(int64_t)e * J.ldx] : 0u;
-            v[e] = !ok ? 0 : (J.in_mode == IN_SIGNED ? (int32_t)u : center(u, J.p, half));
-        }
-    }
-
-    const int bits = J.S == 1 ? 8 : J.bits;
-    const int Rh = 1 << (bits - 1), mask = (1 << bits) - 1;
-    int8_t *dst = J.D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * 16 +
-                  (int64_t)(r % J.RT) * 16;
-    for (int d = 0; d < J.S; ++d) {
-        uint32_t w[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int dig = ((v[e] + Rh) & mask) - Rh; // balanced digit
-            v[e] = (v[e] - dig) >> bits;                // exact division by R
-            w[e >> 2] |= (uint32_t)(dig & 0xFF) << (8 * (e & 3));
-        }
-        *(uint4 *)(dst + (int64_t)d * J.plane) = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-}
-
-__global__ __launch_bounds__(SLICE_THREADS) void k_slice(SliceJob J)
-{
-    slice_one(J, (int64_t)blockIdx.x * SLICE_THREADS + threadIdx.x);
-}
-
-__global__ __launch_bounds__(SLICE_THREADS) void k_slice_batched(
-    const SliceJob *__restrict__ jobs, int njobs)
-{
-    int lo = 0, hi = njobs - 1;
-    const int b = blockIdx.x;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].block_start <= b) lo = mid; else hi = mid - 1;
-    }
-    const SliceJob J = jobs[lo];
-    slice_one(J, (int64_t)(b - J.block_start) * SLICE_THREADS + threadIdx.x);
-}
 
 // ---------------------------------------------------------------------------
 // GEMM on digit planes
@@ -116,6 +49,7 @@ struct Cfg {
     static constexpr int PER_WAVE = (CHUNKS + NW - 1) / NW; // loads per wave (max)
     static_assert(STAGE % 1024 == 0, "stage must be whole 1 KB chunks");
     static_assert((BM * KS) % 1024 == 0 && (BN * KS) % 1024 == 0, "digit blocks");
+    static_assert(BM % 64 == 0 && BN % 64 == 0, "the slicer covers row tiles in blocks of 64");
     static constexpr int H = KS / 32; // 32-deep matrix-core steps per stage
 };
 
@@ -459,26 +393,5 @@ hipError_t launch_i8_batched(int tile, const I8Job *jobs, int njobs, int total,
     }
 }
 
-hipError_t launch_slice(const SliceJob &J, hipStream_t st)
-{
-    const int64_t total = (int64_t)J.rows_pad * (J.KP / 16);
-    const int64_t grid = (total + SLICE_THREADS - 1) / SLICE_THREADS;
-    hipLaunchKernelGGL(k_slice, dim3((unsigned)grid), dim3(SLICE_THREADS), 0, st, J);
-    return hipGetLastError();
-}
-
-hipError_t launch_slice_batched(const SliceJob *dev_jobs, int njobs,
-                                int total_blocks, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_slice_batched, dim3(total_blocks), dim3(SLICE_THREADS), 0, st,
-                       dev_jobs, njobs);
-    return hipGetLastError();
-}
-
-int slice_blocks(const SliceJob &J)
-{
-    const int64_t total = (int64_t)J.rows_pad * (J.KP / 16);
-    return (int)((total + SLICE_THREADS - 1) / SLICE_THREADS);
-}
 
 } // namespace ff

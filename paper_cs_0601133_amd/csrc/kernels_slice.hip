@@ -1,0 +1,83 @@
+// Digit slicer of the INT8 path: operand -> packed signed digit planes.
+//
+// A centered residue c (|c| <= p/2) is written c = sum_{i<S} d_i R^i with
+// R = 2^bits and digits d_i in [-R/2, R/2 - 1] (one direct int8 plane when c
+// already fits int8).  The planes are zero padded and packed: for a row
+// tile of RT rows and the K range padded to KP, the 16-byte group (row r,
+// k/16) of digit d sits at
+//     d*plane + (r/RT)*RT*KP + (k/16)*RT*16 + (r%RT)*16,
+// the layout the INT8 GEMM copies into LDS stage by stage.
+#include "ff_device.h"
+#include "ff_internal.h"
+#include "ff_operand.h"
+
+namespace ff {
+
+namespace {
+
+__device__ __forceinline__ void slice_block(const SliceJob &J, int b, UnitTile &tile)
+{
+    uint32_t u[16];
+    int r, kc;
+    if (!load_unit(J, b, tile, u, r, kc)) return;
+    const uint32_t half = (J.p - 1) / 2;
+    int32_t v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+        v[e] = J.in_mode == IN_SIGNED ? (int32_t)u[e] : center(u[e], J.p, half);
+
+    const int bits = J.S == 1 ? 8 : J.bits;
+    const int Rh = 1 << (bits - 1), mask = (1 << bits) - 1;
+    int8_t *dst = J.D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * 16 +
+                  (int64_t)(r % J.RT) * 16;
+    for (int d = 0; d < J.S; ++d) {
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int dig = ((v[e] + Rh) & mask) - Rh; // balanced digit
+            v[e] = (v[e] - dig) >> bits;                // exact division by R
+            w[e >> 2] |= (uint32_t)(dig & 0xFF) << (8 * (e & 3));
+        }
+        *(uint4 *)(dst + (int64_t)d * J.plane) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+__global__ __launch_bounds__(UNIT_THREADS) void k_slice(SliceJob J)
+{
+    __shared__ UnitTile tile;
+    slice_block(J, blockIdx.x, tile);
+}
+
+__global__ __launch_bounds__(UNIT_THREADS) void k_slice_batched(
+    const SliceJob *__restrict__ jobs, int njobs)
+{
+    __shared__ UnitTile tile;
+    int lo = 0, hi = njobs - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_start <= b) lo = mid; else hi = mid - 1;
+    }
+    const SliceJob J = jobs[lo];
+    slice_block(J, b - J.block_start, tile);
+}
+
+} // namespace
+
+hipError_t launch_slice(const SliceJob &J, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_slice, dim3((unsigned)unit_blocks(J)), dim3(UNIT_THREADS), 0, st, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_batched(const SliceJob *dev_jobs, int njobs,
+                                int total_blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_slice_batched, dim3(total_blocks), dim3(UNIT_THREADS), 0, st,
+                       dev_jobs, njobs);
+    return hipGetLastError();
+}
+
+int slice_blocks(const SliceJob &J) { return unit_blocks(J); }
+
+} // namespace ff

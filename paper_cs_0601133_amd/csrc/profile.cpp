@@ -13,15 +13,15 @@ struct Pair {
     int kind = 0;
 };
 std::mutex g_pmu;
-bool g_on = false;
+int g_mask = 0;
 std::vector<Pair> g_used, g_free;
 } // namespace
 
-bool profiling() { return g_on; }
+bool profiling() { return g_mask != 0; }
 
 void *prof_begin(int kind, hipStream_t st)
 {
-    if (!g_on) return nullptr;
+    if (!(g_mask & (kind == PROF_GEMM ? FF_PROFILE_GEMM : FF_PROFILE_PREP))) return nullptr;
     std::lock_guard<std::mutex> lk(g_pmu);
     Pair p;
     if (!g_free.empty()) {
@@ -54,12 +54,12 @@ using namespace ff;
 
 extern "C" {
 
-int ff_profile_enable(int on)
+int ff_profile_enable(int mask)
 {
     std::lock_guard<std::mutex> lk(g_pmu);
     for (auto &p : g_used) g_free.push_back(p);
     g_used.clear();
-    g_on = on != 0;
+    g_mask = mask & (FF_PROFILE_GEMM | FF_PROFILE_PREP);
     return FF_OK;
 }
 

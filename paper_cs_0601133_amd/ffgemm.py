@@ -26,6 +26,9 @@ FF_PATH_AUTO = 0
 FF_PATH_FP64 = 1
 FF_PATH_INT8 = 2
 
+FF_PROFILE_GEMM = 1
+FF_PROFILE_PREP = 2
+
 _I64 = ctypes.c_int64
 _U32 = ctypes.c_uint32
 _INT = ctypes.c_int
@@ -255,8 +258,11 @@ def ff_autotune(slices, m, n, k):
     return best.value, ms.value
 
 
-def ff_profile_enable(on):
-    return _check(load().ff_profile_enable(int(bool(on))))
+def ff_profile_enable(mask):
+    """mask: FF_PROFILE_GEMM | FF_PROFILE_PREP (True: both), 0 disables."""
+    if mask is True:
+        mask = FF_PROFILE_GEMM | FF_PROFILE_PREP
+    return _check(load().ff_profile_enable(int(mask)))
 
 
 def ff_profile_read():
