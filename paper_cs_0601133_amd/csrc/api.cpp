@@ -262,6 +262,12 @@ void i8_weights(I8Job &J, uint32_t alpha, int bits)
     // every |E_t mod p| <= p/2 + 1 after the floating-point reduction
     const double bound = (2.0 * S - 1.0) * h * (h + 1.0) + (double)J.p;
     J.fp_epi = bound <= 9007199254740992.0 ? 1 : 0;
+    // |E_t| <= S * KP * (R/2)^2 (balanced digits, R = 2^bits; the direct
+    // plane's values are below 2^7); |wc_t| <= p/2.  When the whole sum
+    // stays below 2^53 it is exact in binary64 and one reduction suffices.
+    const double dmax = S == 1 ? 128.0 : (double)(1 << (bits - 1));
+    const double emax = (double)S * (double)J.KP * dmax * dmax;
+    J.epi_direct = J.fp_epi && (2.0 * S - 1.0) * h * emax + (double)J.p <= 9007199254740992.0;
 }
 
 // Packing task of one operand into centered doubles (row tile RT).
@@ -308,10 +314,19 @@ int run_f64_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int6
     // A: rows m, element (i, l) of op(A); B^T: rows n, element (j, l) = op(B)(l, j)
     SliceJob sa = pack_job(A, lda, (int)m, (int)k, transA, in_mode, p, Ad, t.bm(), KP);
     SliceJob sb = pack_job(B, ldb, (int)n, (int)k, transB ? 0 : 1, in_mode, p, Bd, t.bn(), KP);
-    FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_pack_f64(sa, st)));
-    FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_pack_f64(sb, st)));
+    FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_pack_f64_2(sa, sb, st)));
     F64Job J = f64_job(Ad, Bd, C, ldc, m, n, KP, p, alpha, beta, kblock, tile);
+    int kts = 0;
+    const int splits = f64_splits((int64_t)J.tiles_m * J.tiles_n, KP / F64_BK, &kts);
+    if (splits > 1) {
+        // partial products per K split, after the packed operands
+        const int64_t packed = (round_up(m, t.bm()) + round_up(n, t.bn())) * KP * 8;
+        J.kt_split = kts;
+        J.part = (uint32_t *)((char *)ws + round_up(packed, 256));
+    }
     FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_f64(tile, J, st)));
+    if (splits > 1)
+        FF_HIP_CHECK(launch_split_reduce(J.part, splits, m, n, C, ldc, p, alpha, beta, st));
     return FF_OK;
 }
 
@@ -351,8 +366,7 @@ int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
         const uint32_t *Bk = transB ? B + k0 : B + k0 * ldb;
         SliceJob sb = slice_job(Bk, ldb, (int)n, kc, transB ? 0 : 1, IN_RESIDUE, p, P.slices,
                                 P.bits, Bd, t.bn(), KPc);
-        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_slice(sa, st)));
-        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_slice(sb, st)));
+        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_slice2(sa, sb, st)));
         I8Job J;
         std::memset(&J, 0, sizeof(J));
         J.Ad = Ad; J.Bd = Bd; J.a_plane = sa.plane; J.b_plane = sb.plane;

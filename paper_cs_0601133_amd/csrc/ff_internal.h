@@ -44,8 +44,12 @@ struct F64Tile {
 int f64_tile_count();
 const F64Tile &f64_tile(int id);
 int f64_default_tile();
-// The configuration the planner uses (FF_F64_TILE overrides the default).
-int choose_f64_tile();
+// The configuration the planner uses for an m x n product (FF_F64_TILE
+// overrides; m = n = 0: the batched default).
+int choose_f64_tile(int64_t m = 0, int64_t n = 0);
+// Number of K splits of a single FP64 launch with `tiles` workgroup tiles
+// and nk K stages (1: no split), and the stages per split.
+int f64_splits(int64_t tiles, int64_t nk, int *kt_split);
 
 // INT8 kernel: workgroup tile BM x BN, K step 64 bytes, waves of 64 lanes
 // each owning (32*TM) x (32*TN) outputs.  Several configurations per slice
@@ -124,6 +128,12 @@ struct F64Job {
     int gm;             // tile-order group height
     int tiles_m, tiles_n;
     int tile_start;     // first global tile index of this job (batched launches)
+    // Split K (single launches only): with kt_split > 0 the grid holds
+    // tiles_m * tiles_n workgroups per split of kt_split K stages; each
+    // writes its partial product, reduced to [0, p), to part[split][m][n]
+    // and a reduction pass forms C.
+    int kt_split;
+    uint32_t *part;
 };
 
 // Slicing task: one operand of one job into packed digit planes.
@@ -156,6 +166,8 @@ struct I8Job {
     uint32_t w[9];      // alpha * R^t mod p, t = 0 .. 2s-2
     double wc[9];       // the same weights centered, as doubles
     int fp_epi;         // recombine in binary64: (2s-1)(p/2)(p/2+1) + p <= 2^53
+    int epi_direct;     // sum wc_t E_t exactly in binary64 without reducing each E_t:
+                        // (2s-1) max|wc_t| max|E_t| + p <= 2^53 for this job's K
     int gm;             // tile-order group height
     int tiles_m, tiles_n;
     int tile_start;
@@ -175,12 +187,14 @@ void i8_weights(I8Job &J, uint32_t alpha, int bits);
 hipError_t launch_f64(int tile, const F64Job &job, hipStream_t st);
 hipError_t launch_f64_batched(int tile, const F64Job *dev_jobs, int njobs, int total_tiles,
                               int persistent, unsigned *ctr, int fine, hipStream_t st);
-// Operand -> packed centered doubles (SliceJob with S == 0).
-hipError_t launch_pack_f64(const SliceJob &job, hipStream_t st);
+// Operands -> packed centered doubles (SliceJobs with S == 0), both
+// operands of one product in one launch.
+hipError_t launch_pack_f64_2(const SliceJob &a, const SliceJob &b, hipStream_t st);
 hipError_t launch_pack_f64_batched(const SliceJob *dev_jobs, int njobs, int total_blocks,
                                    hipStream_t st);
 
-hipError_t launch_slice(const SliceJob &job, hipStream_t st);
+// Digit slicing of both operands of one product in one launch.
+hipError_t launch_slice2(const SliceJob &a, const SliceJob &b, hipStream_t st);
 hipError_t launch_slice_batched(const SliceJob *dev_jobs, int njobs,
                                 int total_blocks, hipStream_t st);
 
@@ -188,6 +202,12 @@ hipError_t launch_i8(int tile, const I8Job &job, hipStream_t st);
 hipError_t launch_i8_batched(int tile, const I8Job *dev_jobs, int njobs,
                              int total_tiles, int persistent, unsigned *ctr,
                              hipStream_t st);
+
+// C <- (alpha * sum_s part[s] + beta*C) mod p over nsplit partial products
+// part[s][m][n] in [0, p).
+hipError_t launch_split_reduce(const uint32_t *part, int nsplit, int64_t m, int64_t n,
+                               uint32_t *C, int64_t ldc, uint32_t p, uint32_t alpha,
+                               uint32_t beta, hipStream_t st);
 
 // C <- beta*C mod p (beta == 0: C <- 0), m x n, ldc.
 hipError_t launch_scale(uint32_t *C, int64_t ldc, int64_t m, int64_t n,

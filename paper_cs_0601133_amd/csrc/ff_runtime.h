@@ -31,7 +31,8 @@ int pack_blocks(const SliceJob &J);
 F64Job f64_job(const double *Ad, const double *Bd, uint32_t *C, int64_t ldc, int64_t m,
                int64_t n, int KP, uint32_t p, uint32_t alpha, uint32_t beta, int64_t kblock,
                int tile);
-// ws: (round_up(m, bm) + round_up(n, bn)) * round_up(k, 16) doubles.
+// ws: (round_up(m, bm) + round_up(n, bn)) * round_up(k, 16) doubles, then
+// (256-aligned) the split-K partials when f64_splits splits the launch.
 int run_f64_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
                   uint32_t alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
                   uint32_t beta, uint32_t *C, int64_t ldc, int in_mode, int64_t kblock,

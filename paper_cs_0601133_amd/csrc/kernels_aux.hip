@@ -1,5 +1,6 @@
 // Element-wise kernels: C <- beta*C mod p (the k == 0 / alpha == 0 case of
-// the operation) and the optional input-range check.
+// the operation), the sum of split-K partial products with the epilogue, and
+// the optional input-range check.
 #include "ff_device.h"
 #include "ff_internal.h"
 
@@ -37,6 +38,24 @@ __global__ __launch_bounds__(AUX_THREADS) void k_validate(const uint32_t *X, int
     if (cnt) atomicAdd(bad, cnt);
 }
 
+__global__ __launch_bounds__(AUX_THREADS) void k_split_reduce(
+    const uint32_t *part, int nsplit, int64_t m, int64_t n, uint32_t *C, int64_t ldc,
+    uint32_t p, uint32_t alpha, uint32_t beta, double pinv)
+{
+    const int64_t total = m * n;
+    for (int64_t e = (int64_t)blockIdx.x * AUX_THREADS + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * AUX_THREADS) {
+        uint64_t s = 0; // nsplit residues < p < 2^31: no overflow
+        for (int q = 0; q < nsplit; ++q) s += part[(int64_t)q * total + e];
+        const uint32_t r = (uint32_t)(s % p);
+        const int64_t i = e / n, j = e - i * n;
+        uint32_t *cp = C + i * ldc + j;
+        uint32_t out = mulmod(alpha, r, p, pinv);
+        if (beta) out = addmod(out, mulmod(beta, *cp, p, pinv), p);
+        *cp = out;
+    }
+}
+
 int grid_for(int64_t total)
 {
     int64_t g = (total + AUX_THREADS - 1) / AUX_THREADS;
@@ -51,6 +70,15 @@ hipError_t launch_scale(uint32_t *C, int64_t ldc, int64_t m, int64_t n,
 {
     hipLaunchKernelGGL(k_scale, dim3(grid_for(m * n)), dim3(AUX_THREADS), 0, st, C, ldc,
                        m, n, p, beta, 1.0 / (double)p);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_reduce(const uint32_t *part, int nsplit, int64_t m, int64_t n,
+                               uint32_t *C, int64_t ldc, uint32_t p, uint32_t alpha,
+                               uint32_t beta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_split_reduce, dim3(grid_for(m * n)), dim3(AUX_THREADS), 0, st, part,
+                       nsplit, m, n, C, ldc, p, alpha, beta, 1.0 / (double)p);
     return hipGetLastError();
 }
 

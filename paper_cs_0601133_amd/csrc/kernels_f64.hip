@@ -57,10 +57,16 @@ __device__ __forceinline__ void pack_block(const SliceJob &J, int b, UnitTile &t
     for (int c = 0; c < F64_BK / 2; ++c) *(v2d *)(dst + c * 32) = v2d{v[2 * c], v[2 * c + 1]};
 }
 
-__global__ __launch_bounds__(UNIT_THREADS) void k_pack_f64(SliceJob J)
+// Both operands of one product in one launch: blocks [0, blocks_a) pack a,
+// the rest b.
+__global__ __launch_bounds__(UNIT_THREADS) void k_pack_f64_2(SliceJob a, SliceJob b, int blocks_a)
 {
     __shared__ UnitTile tile;
-    pack_block(J, blockIdx.x, tile);
+    const int blk = blockIdx.x;
+    if (blk < blocks_a)
+        pack_block(a, blk, tile);
+    else
+        pack_block(b, blk - blocks_a, tile);
 }
 
 __global__ __launch_bounds__(UNIT_THREADS) void k_pack_f64_batched(
@@ -133,7 +139,7 @@ __device__ __forceinline__ void fold(v4d (&acc)[4][4], double pd, double pinv)
 // (fewer than 16 products fit below 2^53), else every fold_stages stages.
 // SPLIT: schedule for two waves per SIMD (see the loop).
 template <int WGM, int WGN, int NST, bool SPLIT, bool FINE>
-__device__ void f64_tile(const F64Job &J, int tm, int tn, char *smem)
+__device__ void f64_tile(const F64Job &J, int tm, int tn, char *smem, int split)
 {
     using C = F64Cfg<WGM, WGN, NST>;
     const int tid = threadIdx.x;
@@ -146,12 +152,16 @@ __device__ void f64_tile(const F64Job &J, int tm, int tn, char *smem)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    const int nk = J.KP / F64_BK;
+    // K stages [k0, k1) of this tile (all of K unless the launch splits K)
+    const int nkall = J.KP / F64_BK;
+    const int k0 = J.kt_split ? split * J.kt_split : 0;
+    const int k1 = J.kt_split && k0 + J.kt_split < nkall ? k0 + J.kt_split : nkall;
+    const int nk = k1 - k0;
     int per_stage = 0;
 #pragma unroll
     for (int st = 0; st < NST - 1; ++st)
-        per_stage = issue_stage<C>(J, tm, tn, st < nk ? st : nk - 1, smem + st * C::STAGE, wave,
-                                   lane);
+        per_stage = issue_stage<C>(J, tm, tn, k0 + (st < nk ? st : nk - 1), smem + st * C::STAGE,
+                                   wave, lane);
 
     // Fragment offsets inside a stage: in 16-row block b (2048 bytes), lane
     // l reads the 16-byte word of row l%16 holding K values 4(l/16) + 2h, +1.
@@ -175,8 +185,8 @@ __device__ void f64_tile(const F64Job &J, int tm, int tn, char *smem)
                 b[h][j] = *(const v2d *)(cur + C::A_BYTES + ((wn0 >> 4) + j) * 2048 + frag + h * 256);
         }
         const int nxt = kt + NST - 1;
-        issue_stage<C>(J, tm, tn, nxt < nk ? nxt : nk - 1, smem + (nxt % NST) * C::STAGE, wave,
-                       lane);
+        issue_stage<C>(J, tm, tn, k0 + (nxt < nk ? nxt : nk - 1), smem + (nxt % NST) * C::STAGE,
+                       wave, lane);
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -241,6 +251,10 @@ __device__ void f64_tile(const F64Job &J, int tm, int tn, char *smem)
                 const int gc = n0 + wn0 + j * 16 + (lane & 15);
                 if (gr < J.m && gc < J.n) {
                     const uint32_t v = canon_f64(acc[i][j][r], J.pd, J.pinv, J.p);
+                    if (J.part) {
+                        J.part[((int64_t)split * J.m + gr) * J.n + gc] = v;
+                        continue;
+                    }
                     uint32_t out = mulmod(J.alpha, v, J.p, J.pinv);
                     uint32_t *cp = J.C + (int64_t)gr * J.ldc + gc;
                     if (J.beta) out = addmod(out, mulmod(J.beta, *cp, J.p, J.pinv), J.p);
@@ -259,10 +273,11 @@ void k_fgemm_f64(F64Job J)
 {
     __shared__ __attribute__((aligned(1024))) char smem[F64Cfg<WGM, WGN, NST>::BYTES];
     const int G = J.tiles_m * J.tiles_n;
-    const int t = xcd_remap(blockIdx.x, G);
+    const int split = (int)blockIdx.x / G; // 0 unless the launch splits K
+    const int t = xcd_remap((int)blockIdx.x - split * G, G);
     int tm, tn;
     grouped_tile_rt(t, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
-    f64_tile<WGM, WGN, NST, (WPE > 1), FINE>(J, tm, tn, smem);
+    f64_tile<WGM, WGN, NST, (WPE > 1), FINE>(J, tm, tn, smem, split);
 }
 
 // Every job of the table must have fold_stages == 0 iff FINE.
@@ -291,7 +306,7 @@ void k_fgemm_f64_batched(const F64Job *__restrict__ jobs, int njobs, int total, 
         const F64Job J = jobs[lo];
         int tm, tn;
         grouped_tile_rt(g - J.tile_start, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
-        f64_tile<WGM, WGN, NST, (WPE > 1), FINE>(J, tm, tn, smem);
+        f64_tile<WGM, WGN, NST, (WPE > 1), FINE>(J, tm, tn, smem, 0);
         if (!persistent) break;
     }
     if (persistent && threadIdx.x == 0) {
@@ -309,7 +324,9 @@ void k_fgemm_f64_batched(const F64Job *__restrict__ jobs, int njobs, int total, 
 template <int WGM, int WGN, int NST, int WPE>
 hipError_t run_single(const F64Job &J, hipStream_t st)
 {
-    const int G = J.tiles_m * J.tiles_n;
+    const int nk = J.KP / F64_BK;
+    const int splits = J.kt_split ? (nk + J.kt_split - 1) / J.kt_split : 1;
+    const int G = J.tiles_m * J.tiles_n * splits;
     if (J.fold_stages > 0)
         hipLaunchKernelGGL((k_fgemm_f64<WGM, WGN, NST, WPE, false>), dim3(G),
                            dim3(64 * WGM * WGN), 0, st, J);
@@ -377,9 +394,11 @@ hipError_t launch_f64_batched(int tile, const F64Job *jobs, int njobs, int total
     }
 }
 
-hipError_t launch_pack_f64(const SliceJob &J, hipStream_t st)
+hipError_t launch_pack_f64_2(const SliceJob &a, const SliceJob &b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pack_f64, dim3((unsigned)unit_blocks(J)), dim3(UNIT_THREADS), 0, st, J);
+    const int na = unit_blocks(a), nb = unit_blocks(b);
+    hipLaunchKernelGGL(k_pack_f64_2, dim3((unsigned)(na + nb)), dim3(UNIT_THREADS), 0, st, a, b,
+                       na);
     return hipGetLastError();
 }
 

@@ -197,9 +197,10 @@ __device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
     __syncthreads();
 
     // Epilogue.  32 x 32 accumulator layout: lane holds column lane%32 and
-    // rows 8*(v/4) + 4*(lane/32) + v%4, v = 0..15.  With fp_epi the digit
-    // sums are recombined exactly in binary64 (centered weights, centered
-    // E_t mod p), else in 64-bit integers with a reduction per term.
+    // rows 8*(v/4) + 4*(lane/32) + v%4, v = 0..15.  With epi_direct the
+    // digit sums are recombined in one exact binary64 sum with centered
+    // weights; with fp_epi each E_t is first reduced (centered) in binary64;
+    // otherwise 64-bit integers with a reduction per term.
     const int m0 = tm * C::BM, n0 = tn * C::BN;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -211,7 +212,13 @@ __device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
                 const int col = n0 + wn0 + 32 * j + (lane & 31);
                 if (row < J.m && col < J.n) {
                     uint32_t r;
-                    if (J.fp_epi) {
+                    if (J.epi_direct) {
+                        double sum = 0.0;
+#pragma unroll
+                        for (int t = 0; t < C::NSET; ++t)
+                            sum = __builtin_fma(J.wc[t], (double)acc[t][i][j][v], sum);
+                        r = canon_f64(sum, J.pd, J.pinv, J.p);
+                    } else if (J.fp_epi) {
                         double sum = 0.0;
 #pragma unroll
                         for (int t = 0; t < C::NSET; ++t) {

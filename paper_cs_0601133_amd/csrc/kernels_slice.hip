@@ -42,10 +42,16 @@ __device__ __forceinline__ void slice_block(const SliceJob &J, int b, UnitTile &
     }
 }
 
-__global__ __launch_bounds__(UNIT_THREADS) void k_slice(SliceJob J)
+// Both operands of one product in one launch: blocks [0, blocks_a) slice
+// a, the rest b.
+__global__ __launch_bounds__(UNIT_THREADS) void k_slice2(SliceJob a, SliceJob b, int blocks_a)
 {
     __shared__ UnitTile tile;
-    slice_block(J, blockIdx.x, tile);
+    const int blk = blockIdx.x;
+    if (blk < blocks_a)
+        slice_block(a, blk, tile);
+    else
+        slice_block(b, blk - blocks_a, tile);
 }
 
 __global__ __launch_bounds__(UNIT_THREADS) void k_slice_batched(
@@ -64,9 +70,10 @@ __global__ __launch_bounds__(UNIT_THREADS) void k_slice_batched(
 
 } // namespace
 
-hipError_t launch_slice(const SliceJob &J, hipStream_t st)
+hipError_t launch_slice2(const SliceJob &a, const SliceJob &b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_slice, dim3((unsigned)unit_blocks(J)), dim3(UNIT_THREADS), 0, st, J);
+    const int na = unit_blocks(a), nb = unit_blocks(b);
+    hipLaunchKernelGGL(k_slice2, dim3((unsigned)(na + nb)), dim3(UNIT_THREADS), 0, st, a, b, na);
     return hipGetLastError();
 }
 

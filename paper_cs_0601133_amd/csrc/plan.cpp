@@ -135,15 +135,29 @@ int crossover_w()
 
 } // namespace
 
-// FF_F64_TILE (an id) overrides the default FP64 configuration.
-int choose_f64_tile()
+// FF_F64_TILE (an id) overrides the default FP64 configuration; products
+// of at most 1024 x 1024 take the 128 x 128 tile (more workgroups).
+int choose_f64_tile(int64_t m, int64_t n)
 {
     const char *e = std::getenv("FF_F64_TILE");
     if (e && *e) {
         const int id = std::atoi(e);
         if (id >= 0 && id < f64_tile_count()) return id;
     }
+    if (m > 0 && n > 0 && m * n <= 1024 * 1024) return 2;
     return f64_default_tile();
+}
+
+// A single FP64 launch with fewer than 128 workgroup tiles splits K so that
+// about 512 workgroups run (a wave's 64 x 64 block over all of K is a long
+// serial chain of matrix-core steps, and a few tiles leave most CUs idle).
+int f64_splits(int64_t tiles, int64_t nk, int *kt_split)
+{
+    int64_t s = 1;
+    if (tiles < 128 && nk > 1) s = std::min<int64_t>(nk, std::max<int64_t>(1, 512 / tiles));
+    const int64_t per = (nk + s - 1) / s;
+    *kt_split = s > 1 ? (int)per : 0;
+    return s > 1 ? (int)((nk + per - 1) / per) : 1;
 }
 
 int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
@@ -206,7 +220,7 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         P.hi = reduce ? wid_r.hi : wid_d.hi;
         P.max_prod = reduce ? mp_r : mp_d;
         P.kblock = kb;
-        P.tile = choose_f64_tile();
+        P.tile = choose_f64_tile(P.me >> L, P.ne >> L);
     } else {
         int best_s = 0, best_bits = 0, best_reduce = 0;
         for (int reduce = 0; reduce <= (L > 0 ? 1 : 0); ++reduce) {
@@ -258,7 +272,13 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         const int64_t mp = round_up(std::max<int64_t>(ml, 1), t.bm());
         const int64_t np = round_up(std::max<int64_t>(nl, 1), t.bn());
         ws += nleaf * (mp + np) * KP * 8;
-        if (L > 0) ws += nleaf * (ml * kl + kl * nl) * 4 + nleaf * ml * nl * 4 + 256;
+        if (L > 0) {
+            ws += nleaf * (ml * kl + kl * nl) * 4 + nleaf * ml * nl * 4 + 256;
+        } else {
+            int kts = 0;
+            const int ns = f64_splits((mp / t.bm()) * (np / t.bn()), KP / F64_BK, &kts);
+            if (ns > 1) ws += 256 + (int64_t)ns * ml * nl * 4; // split partials
+        }
     }
     if (L > 0) ws += nleaf * 256 + 4096; // job tables
     P.ws_bytes = ws;
