@@ -97,6 +97,19 @@ def library_path():
     return os.environ.get("FF_LIBRARY") or _build.LIB
 
 
+def _init_torch_runtime():
+    # Loaded after torch, the library resolves to torch's HIP runtime, and
+    # torch must initialise that runtime itself: its own initialisation
+    # reports no devices when another caller (a library call) initialised it
+    # first.  So torch is imported and initialised before the library loads.
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load():
     """Load libffgemm.so (it must have been built: see build.py)."""
     global _lib
@@ -106,6 +119,7 @@ def load():
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: the HIP library has not been built "
                            "(python -m paper_cs_0601133_amd.build)")
+    _init_torch_runtime()
     lib = ctypes.CDLL(path)
     for name, (args, res) in _SIGS.items():
         fn = getattr(lib, name)
