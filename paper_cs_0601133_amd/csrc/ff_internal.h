@@ -62,6 +62,7 @@ struct I8Tile {
     int WGM, WGN;
     int KS;     // K bytes per LDS stage (32 or 64)
     int GM;     // tile rows per group of the tile order (L2 reuse)
+    int pipe;   // next stage's fragments read while the current one computes
     int bm() const { return WGM * 32 * TM; }
     int bn() const { return WGN * 32 * TN; }
     int threads() const { return 64 * WGM * WGN; }

@@ -107,12 +107,83 @@ __device__ __forceinline__ uint32_t mod_i32(int32_t e, uint32_t p, double pd, do
     return (uint32_t)ri;
 }
 
+// Matrix-core fragments of one K stage: lane l holds the 16-byte group (row
+// l%32, K half l/32) of each digit block of its rows (a) and columns (b).
+template <int SE, int TM, int TN, int H>
+struct Frags {
+    v4i a[H][SE][TM];
+    v4i b[H][SE][TN];
+};
+
+template <class C, int SE, int TM, int TN>
+__device__ __forceinline__ void read_frags(Frags<SE, TM, TN, C::H> &f, const char *cur, int wm0,
+                                           int wn0, int lane)
+{
+    constexpr int KS = C::H * 32;
+#pragma unroll
+    for (int h = 0; h < C::H; ++h) {
+        const int cidx = 2 * h + (lane >> 5);
+#pragma unroll
+        for (int d = 0; d < SE; ++d) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                f.a[h][d][i] = *(const v4i *)(cur + d * C::BM * KS +
+                                              (cidx * C::BM + wm0 + 32 * i + (lane & 31)) * 16);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                f.b[h][d][j] = *(const v4i *)(cur + C::A_BYTES + d * C::BN * KS +
+                                              (cidx * C::BN + wn0 + 32 * j + (lane & 31)) * 16);
+        }
+    }
+}
+
+template <class C, int SE, int TM, int TN>
+__device__ __forceinline__ void mfma_stage(v16i (&acc)[C::NSET][TM][TN],
+                                           const Frags<SE, TM, TN, C::H> &f)
+{
+#pragma unroll
+    for (int h = 0; h < C::H; ++h)
+#pragma unroll
+        for (int da = 0; da < SE; ++da)
+#pragma unroll
+            for (int db = 0; db < SE; ++db)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                            f.a[h][da][i], f.b[h][db][j], acc[da + db][i][j], 0, 0, 0);
+}
+
+// Schedule of one stage: the fragment reads first, then the stage loads
+// spread between the matrix-core instructions so that no burst of memory
+// instructions holds up the matrix core.
+template <class C, int SE, int TM, int TN>
+__device__ __forceinline__ void stage_schedule()
+{
+    constexpr int NDS = C::H * SE * (TM + TN);
+    constexpr int NMF = C::H * SE * SE * TM * TN;
+    constexpr int NLD = C::PER_WAVE;
+    constexpr int GAP = NMF / (NLD + 1);
+    __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, GAP, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, NMF - NLD * GAP, 0);
+}
+
 // One output tile with SE digits per operand; smem holds NST stages of the
 // layout for SE digits (the ring is sized for the configuration's maximum).
-template <int SE, int TM, int TN, int WGM, int WGN, int KS, int NST>
+// PIPE: the fragments of stage kt+1 are read while stage kt's matrix-core
+// work runs (two fragment sets in registers), so the LDS reads that follow
+// every barrier no longer stall the matrix core.
+template <int SE, int TM, int TN, int WGM, int WGN, int KS, int NST, bool PIPE>
 __device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
 {
     using C = Cfg<SE, TM, TN, WGM, WGN, KS>;
+    using F = Frags<SE, TM, TN, C::H>;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * 32 * TM, wn0 = (wave % WGN) * 32 * TN;
@@ -128,68 +199,65 @@ __device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
                 for (int v = 0; v < 16; ++v) acc[t][i][j][v] = 0;
 
     const int nk = J.KP / KS;
-    // prologue: stages 0 .. NST-2 in flight (stage indices past the end are
-    // clamped: those loads refill a free slot with data nobody reads)
-    int per_stage = 0;
+    if constexpr (!PIPE) {
+        // prologue: stages 0 .. NST-2 in flight (stage indices past the end
+        // are clamped: those loads refill a free slot with data nobody reads)
+        int per_stage = 0;
 #pragma unroll
-    for (int st = 0; st < NST - 1; ++st)
-        per_stage = issue_stage<C>(J, tm, tn, st < nk ? st : nk - 1, smem + st * C::STAGE,
-                                   wave, lane);
-
-    for (int kt = 0; kt < nk; ++kt) {
-        // Stage kt has landed once at most the NST-2 later stages' loads of
-        // this wave are outstanding; after the barrier every wave's part is
-        // in LDS, and the slot of stage kt-1 is free for stage kt+NST-1.
-        wait_vm((NST - 2) * per_stage);
+        for (int st = 0; st < NST - 1; ++st)
+            per_stage = issue_stage<C>(J, tm, tn, st < nk ? st : nk - 1, smem + st * C::STAGE,
+                                       wave, lane);
+        for (int kt = 0; kt < nk; ++kt) {
+            // Stage kt has landed once at most the NST-2 later stages' loads
+            // of this wave are outstanding; after the barrier every wave's
+            // part is in LDS, and the slot of stage kt-1 is free for stage
+            // kt+NST-1.
+            wait_vm((NST - 2) * per_stage);
+            ring_barrier();
+            F f;
+            read_frags<C>(f, smem + (kt % NST) * C::STAGE, wm0, wn0, lane);
+            const int nxt = kt + NST - 1;
+            issue_stage<C>(J, tm, tn, nxt < nk ? nxt : nk - 1, smem + (nxt % NST) * C::STAGE,
+                           wave, lane);
+            mfma_stage<C>(acc, f);
+            stage_schedule<C, SE, TM, TN>();
+        }
+    } else {
+        // prologue: all NST slots in flight; stage 0's fragments in f0
+        int per_stage = 0;
+#pragma unroll
+        for (int st = 0; st < NST; ++st)
+            per_stage = issue_stage<C>(J, tm, tn, st < nk ? st : nk - 1, smem + st * C::STAGE,
+                                       wave, lane);
+        wait_vm((NST - 1) * per_stage);
         ring_barrier();
-        const char *cur = smem + (kt % NST) * C::STAGE;
-        // Fragments of the stage's 32-deep K steps: lane l reads its 16-byte
-        // group (row l%32, K half l/32) of each digit block.
-        v4i a[C::H][SE][TM], b[C::H][SE][TN];
-#pragma unroll
-        for (int h = 0; h < C::H; ++h) {
-            const int cidx = 2 * h + (lane >> 5);
-#pragma unroll
-            for (int d = 0; d < SE; ++d) {
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-                    a[h][d][i] = *(const v4i *)(cur + d * C::BM * KS +
-                                                (cidx * C::BM + wm0 + 32 * i + (lane & 31)) * 16);
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    b[h][d][j] = *(const v4i *)(cur + C::A_BYTES + d * C::BN * KS +
-                                                (cidx * C::BN + wn0 + 32 * j + (lane & 31)) * 16);
-            }
+        F f0, f1;
+        read_frags<C>(f0, smem, wm0, wn0, lane);
+        // One step: stage kt's matrix-core work on cur while stage kt+1's
+        // fragments are read into nxt.  Before the barrier each wave has
+        // its earlier fragment reads back (lgkmcnt(0)) and its loads of
+        // stage kt+1 landed (stages up to kt+NST-1 were issued, at most
+        // NST-2 later ones may still be in flight); after it, the slot of
+        // stage kt (its fragments are in registers on every wave) takes
+        // stage kt+NST.  On the last step the read of "stage kt+1" hits a
+        // slot that holds a clamped copy nobody uses.
+        auto step = [&](int kt, F &cur, F &nxt) {
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            wait_vm((NST - 2) * per_stage);
+            ring_barrier();
+            const int nst = kt + NST;
+            issue_stage<C>(J, tm, tn, nst < nk ? nst : nk - 1, smem + (kt % NST) * C::STAGE,
+                           wave, lane);
+            read_frags<C>(nxt, smem + ((kt + 1) % NST) * C::STAGE, wm0, wn0, lane);
+            mfma_stage<C>(acc, cur);
+            stage_schedule<C, SE, TM, TN>();
+        };
+        int kt = 0;
+        for (; kt + 1 < nk; kt += 2) {
+            step(kt, f0, f1);
+            step(kt + 1, f1, f0);
         }
-        const int nxt = kt + NST - 1;
-        issue_stage<C>(J, tm, tn, nxt < nk ? nxt : nk - 1, smem + (nxt % NST) * C::STAGE, wave,
-                       lane);
-#pragma unroll
-        for (int h = 0; h < C::H; ++h)
-#pragma unroll
-            for (int da = 0; da < SE; ++da)
-#pragma unroll
-                for (int db = 0; db < SE; ++db)
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                a[h][da][i], b[h][db][j], acc[da + db][i][j], 0, 0, 0);
-        // Schedule: the fragment reads first, then the next stage's loads
-        // spread between the matrix-core instructions so that no burst of
-        // memory instructions holds up the matrix core.
-        constexpr int NDS = C::H * SE * (TM + TN);
-        constexpr int NMF = C::H * SE * SE * TM * TN;
-        constexpr int NLD = C::PER_WAVE;
-        constexpr int GAP = NMF / (NLD + 1);
-        __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);
-#pragma unroll
-        for (int q = 0; q < NLD; ++q) {
-            __builtin_amdgcn_sched_group_barrier(0x008, GAP, 0);
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, NMF - NLD * GAP, 0);
+        if (kt < nk) step(kt, f0, f1);
     }
     // drain the (dummy) loads still in flight before the ring is left
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -247,7 +315,7 @@ struct Wpe {
     static constexpr int v = (WGM * WGN) / 4 > 0 ? (WGM * WGN) / 4 : 1;
 };
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
                           amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
 void k_fgemm_i8(I8Job J)
@@ -258,25 +326,25 @@ void k_fgemm_i8(I8Job J)
     const int t = xcd_remap(blockIdx.x, G);
     int tm, tn;
     grouped_tile_rt(t, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
-    i8_tile<S, TM, TN, WGM, WGN, KS, R::NST>(J, tm, tn, smem);
+    i8_tile<S, TM, TN, WGM, WGN, KS, R::NST, PIPE>(J, tm, tn, smem);
 }
 
 // Batched: a job may use fewer digits than the configuration's S; the tile
 // body is specialised per digit count so that no matrix-core instruction is
 // predicated.
-template <int S, int TM, int TN, int WGM, int WGN, int KS, int NST>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, int NST, bool PIPE>
 __device__ __forceinline__ void i8_tile_any(const I8Job &J, int tm, int tn, char *smem)
 {
     if constexpr (S >= 1) {
         if (J.s == S) {
-            i8_tile<S, TM, TN, WGM, WGN, KS, NST>(J, tm, tn, smem);
+            i8_tile<S, TM, TN, WGM, WGN, KS, NST, PIPE>(J, tm, tn, smem);
             return;
         }
     }
-    if constexpr (S > 1) i8_tile_any<S - 1, TM, TN, WGM, WGN, KS, NST>(J, tm, tn, smem);
+    if constexpr (S > 1) i8_tile_any<S - 1, TM, TN, WGM, WGN, KS, NST, PIPE>(J, tm, tn, smem);
 }
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
                           amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
 void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
@@ -302,7 +370,7 @@ void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
         const I8Job J = jobs[lo];
         int tm, tn;
         grouped_tile_rt(g - J.tile_start, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
-        i8_tile_any<S, TM, TN, WGM, WGN, KS, R::NST>(J, tm, tn, smem);
+        i8_tile_any<S, TM, TN, WGM, WGN, KS, R::NST, PIPE>(J, tm, tn, smem);
         if (!persistent) break;
     }
     if (persistent && threadIdx.x == 0) {
@@ -315,16 +383,16 @@ void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
     }
 }
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
 hipError_t run_single(const I8Job &J, hipStream_t st)
 {
     const int G = J.tiles_m * J.tiles_n;
-    hipLaunchKernelGGL((k_fgemm_i8<S, TM, TN, WGM, WGN, KS>), dim3(G), dim3(64 * WGM * WGN),
-                       0, st, J);
+    hipLaunchKernelGGL((k_fgemm_i8<S, TM, TN, WGM, WGN, KS, PIPE>), dim3(G),
+                       dim3(64 * WGM * WGN), 0, st, J);
     return hipGetLastError();
 }
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
 hipError_t run_batched(const I8Job *jobs, int njobs, int total, int persistent,
                        unsigned *ctr, hipStream_t st)
 {
@@ -336,41 +404,47 @@ hipError_t run_batched(const I8Job *jobs, int njobs, int total, int persistent,
         grid = cus < total ? cus : total;
         if (grid < 1) grid = 1;
     }
-    hipLaunchKernelGGL((k_fgemm_i8_batched<S, TM, TN, WGM, WGN, KS>), dim3(grid),
+    hipLaunchKernelGGL((k_fgemm_i8_batched<S, TM, TN, WGM, WGN, KS, PIPE>), dim3(grid),
                        dim3(64 * WGM * WGN), 0, st, jobs, njobs, total, persistent, ctr);
     return hipGetLastError();
 }
 
 } // namespace
 
-// Compiled configurations: id, S, TM, TN, WGM, WGN, KS, GM.  Each
+// Compiled configurations: id, S, TM, TN, WGM, WGN, KS, GM, PIPE.  Each
 // (WGM x WGN) workgroup of 64-lane waves owns a (WGM*32*TM) x (WGN*32*TN)
 // tile of C; 2S-1 accumulator sets of TM*TN 32x32 blocks live in each wave;
-// KS bytes of K per LDS stage; GM tile rows per group of the tile order.
+// KS bytes of K per LDS stage; GM tile rows per group of the tile order;
+// PIPE: fragment reads of the next stage overlap the current stage.
 #define FF_I8_TILES(X)                                                            \
-    X(0, 1, 2, 2, 2, 2, 64, 8)  /* 128 x 128, 4 waves,   64 acc */                \
-    X(1, 1, 2, 2, 4, 2, 64, 8)  /* 256 x 128, 8 waves,   64 acc */                \
-    X(2, 1, 2, 2, 4, 2, 32, 8)  /* 256 x 128, 8 waves, half stages */             \
-    X(3, 2, 1, 2, 4, 2, 32, 8)  /* 128 x 128, 8 waves,   96 acc, half stages */   \
-    X(4, 2, 1, 2, 4, 2, 64, 8)  /* 128 x 128, 8 waves,   96 acc */                \
-    X(5, 3, 1, 2, 4, 2, 32, 8)  /* 128 x 128, 8 waves,  160 acc, half stages */   \
-    X(6, 3, 1, 2, 4, 2, 64, 8)  /* 128 x 128, 8 waves,  160 acc */                \
-    X(7, 3, 1, 1, 4, 2, 64, 8)  /* 128 x  64, 8 waves,   80 acc */                \
-    X(8, 4, 1, 1, 4, 2, 64, 8)  /* 128 x  64, 8 waves,  112 acc */                \
-    X(9, 4, 1, 1, 4, 2, 64, 4)  /* 128 x  64, 8 waves,  groups of 4 */            \
-    X(10, 4, 1, 1, 2, 4, 64, 8) /*  64 x 128, 8 waves,  112 acc */                \
-    X(11, 4, 1, 1, 4, 2, 32, 4) /* 128 x  64, half stages, groups of 4 */         \
-    X(12, 5, 1, 1, 4, 2, 64, 8) /* 128 x  64, 8 waves,  144 acc */                \
-    X(13, 4, 1, 1, 4, 2, 32, 8) /* 128 x  64, half stages */
+    X(0, 1, 2, 2, 2, 2, 64, 8, 0)  /* 128 x 128, 4 waves,   64 acc */             \
+    X(1, 1, 2, 2, 4, 2, 64, 8, 0)  /* 256 x 128, 8 waves,   64 acc */             \
+    X(2, 1, 2, 2, 4, 2, 32, 8, 0)  /* 256 x 128, 8 waves, half stages */          \
+    X(3, 2, 1, 2, 4, 2, 32, 8, 0)  /* 128 x 128, 8 waves,   96 acc, half stages */\
+    X(4, 2, 1, 2, 4, 2, 64, 8, 0)  /* 128 x 128, 8 waves,   96 acc */             \
+    X(5, 3, 1, 2, 4, 2, 32, 8, 0)  /* 128 x 128, 8 waves,  160 acc, half stages */\
+    X(6, 3, 1, 2, 4, 2, 64, 8, 0)  /* 128 x 128, 8 waves,  160 acc */             \
+    X(7, 3, 1, 1, 4, 2, 64, 8, 0)  /* 128 x  64, 8 waves,   80 acc */             \
+    X(8, 4, 1, 1, 4, 2, 64, 8, 0)  /* 128 x  64, 8 waves,  112 acc */             \
+    X(9, 4, 1, 1, 4, 2, 64, 4, 0)  /* 128 x  64, 8 waves,  groups of 4 */         \
+    X(10, 4, 1, 1, 2, 4, 64, 8, 0) /*  64 x 128, 8 waves,  112 acc */             \
+    X(11, 4, 1, 1, 4, 2, 32, 4, 0) /* 128 x  64, half stages, groups of 4 */      \
+    X(12, 5, 1, 1, 4, 2, 64, 8, 0) /* 128 x  64, 8 waves,  144 acc */             \
+    X(13, 4, 1, 1, 4, 2, 32, 8, 0) /* 128 x  64, half stages */                   \
+    X(14, 4, 1, 1, 4, 2, 32, 8, 1) /* 128 x  64, half stages, pipelined */        \
+    X(15, 4, 1, 1, 4, 2, 64, 8, 1) /* 128 x  64, pipelined */                     \
+    X(16, 3, 1, 2, 4, 2, 32, 8, 1) /* 128 x 128, half stages, pipelined */        \
+    X(17, 1, 2, 2, 4, 2, 32, 8, 1) /* 256 x 128, half stages, pipelined */        \
+    X(18, 2, 1, 2, 4, 2, 32, 8, 1) /* 128 x 128, half stages, pipelined */
 
 namespace {
 const I8Tile k_tiles[] = {
-#define FF_ROW(id, S, TM, TN, WGM, WGN, KS, GM) I8Tile{id, S, TM, TN, WGM, WGN, KS, GM},
+#define FF_ROW(id, S, TM, TN, WGM, WGN, KS, GM, PIPE) I8Tile{id, S, TM, TN, WGM, WGN, KS, GM, PIPE},
     FF_I8_TILES(FF_ROW)
 #undef FF_ROW
 };
 // Default configuration per slice count (index = S).
-const int k_default[6] = {-1, 1, 4, 6, 8, 12};
+const int k_default[6] = {-1, 1, 4, 6, 15, 12};
 } // namespace
 
 int i8_tile_count() { return (int)(sizeof(k_tiles) / sizeof(k_tiles[0])); }
@@ -380,8 +454,8 @@ int i8_default_tile(int S) { return (S >= 1 && S <= 5) ? k_default[S] : -1; }
 hipError_t launch_i8(int tile, const I8Job &J, hipStream_t st)
 {
     switch (tile) {
-#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM)                                    \
-    case id: return run_single<S, TM, TN, WGM, WGN, KS>(J, st);
+#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE)                              \
+    case id: return run_single<S, TM, TN, WGM, WGN, KS, PIPE>(J, st);
         FF_I8_TILES(FF_CASE)
 #undef FF_CASE
     default: return hipErrorInvalidValue;
@@ -392,8 +466,9 @@ hipError_t launch_i8_batched(int tile, const I8Job *jobs, int njobs, int total,
                              int persistent, unsigned *ctr, hipStream_t st)
 {
     switch (tile) {
-#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM)                                    \
-    case id: return run_batched<S, TM, TN, WGM, WGN, KS>(jobs, njobs, total, persistent, ctr, st);
+#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE)                              \
+    case id:                                                                          \
+        return run_batched<S, TM, TN, WGM, WGN, KS, PIPE>(jobs, njobs, total, persistent, ctr, st);
         FF_I8_TILES(FF_CASE)
 #undef FF_CASE
     default: return hipErrorInvalidValue;
