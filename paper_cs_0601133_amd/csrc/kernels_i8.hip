@@ -435,7 +435,8 @@ hipError_t run_batched(const I8Job *jobs, int njobs, int total, int persistent,
     X(15, 4, 1, 1, 4, 2, 64, 8, 1) /* 128 x  64, pipelined */                     \
     X(16, 3, 1, 2, 4, 2, 32, 8, 1) /* 128 x 128, half stages, pipelined */        \
     X(17, 1, 2, 2, 4, 2, 32, 8, 1) /* 256 x 128, half stages, pipelined */        \
-    X(18, 2, 1, 2, 4, 2, 32, 8, 1) /* 128 x 128, half stages, pipelined */
+    X(18, 2, 1, 2, 4, 2, 32, 8, 1) /* 128 x 128, half stages, pipelined */        \
+    X(19, 1, 2, 4, 4, 2, 64, 8, 0) /* 256 x 256, 8 waves,  128 acc */
 
 namespace {
 const I8Tile k_tiles[] = {
@@ -444,7 +445,7 @@ const I8Tile k_tiles[] = {
 #undef FF_ROW
 };
 // Default configuration per slice count (index = S).
-const int k_default[6] = {-1, 1, 4, 6, 15, 12};
+const int k_default[6] = {-1, 19, 4, 6, 15, 12};
 } // namespace
 
 int i8_tile_count() { return (int)(sizeof(k_tiles) / sizeof(k_tiles[0])); }
