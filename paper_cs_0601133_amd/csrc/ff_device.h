@@ -8,18 +8,21 @@
 
 namespace ff {
 
-// (a * b) mod p for a, b < p < 2^31.  The quotient estimate from the
-// double-precision inverse is off by at most one, so the remainder lands in
-// [-p, 2p) and one correction on each side makes it canonical.
+// (a * b) mod p for a, b < p < 2^31, in binary64 and 32-bit integers.  The
+// exact product is hi + lo with hi = fl(ab) and lo = fma(a, b, -hi) (exact,
+// |lo| <= 2^8).  q = rint(hi/p) computed with the rounded inverse is within
+// one of the nearest integer to hi/p, so hi - qp is an exact small integer
+// (the fma rounds nothing) and r = hi - qp + lo lies in (-p, p); one
+// correction makes it canonical.
 __device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, uint32_t p,
                                            double pinv)
 {
-    const uint64_t ab = (uint64_t)a * b;
-    const uint64_t q = (uint64_t)((double)a * (double)b * pinv);
-    int64_t r = (int64_t)(ab - q * (uint64_t)p);
-    r += (r < 0) ? (int64_t)p : 0;
-    r -= (r >= (int64_t)p) ? (int64_t)p : 0;
-    return (uint32_t)r;
+    const double ad = (double)a, bd = (double)b, pd = (double)p;
+    const double hi = ad * bd;
+    const double lo = __builtin_fma(ad, bd, -hi);
+    const double q = __builtin_rint(hi * pinv);
+    const int32_t r = (int32_t)(__builtin_fma(-q, pd, hi) + lo);
+    return (uint32_t)(r < 0 ? r + (int32_t)p : r);
 }
 
 __device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t p)
@@ -29,19 +32,19 @@ __device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t p)
 }
 
 // Canonical residue of an integer-valued double x with |x| <= 2^53:
-// r = x - p*rint(x/p) is exact (an integer of magnitude <= p/2 + 2) and is
-// then moved into [0, p).
+// r = x - p*rint(x/p) is exact with |r| <= p/2 + 2 (the quotient estimate
+// from the rounded inverse is off by at most one), so it converts to 32 bits
+// exactly; two corrections each side cover p = 2 and 3.
 __device__ __forceinline__ uint32_t canon_f64(double x, double pd, double pinv,
                                               uint32_t p)
 {
     const double q = __builtin_rint(x * pinv);
-    const double r = __builtin_fma(-q, pd, x);
-    int64_t ri = (int64_t)r;
-    ri += (ri < 0) ? (int64_t)p : 0;
-    ri += (ri < 0) ? (int64_t)p : 0;
-    ri -= (ri >= (int64_t)p) ? (int64_t)p : 0;
-    ri -= (ri >= (int64_t)p) ? (int64_t)p : 0;
-    return (uint32_t)ri;
+    int32_t r = (int32_t)__builtin_fma(-q, pd, x);
+    r += r < 0 ? (int32_t)p : 0;
+    r += r < 0 ? (int32_t)p : 0;
+    r -= r >= (int32_t)p ? (int32_t)p : 0;
+    r -= r >= (int32_t)p ? (int32_t)p : 0;
+    return (uint32_t)r;
 }
 
 // Centered value of a residue u in [0, p): u or u - p.

@@ -139,7 +139,7 @@ __device__ __forceinline__ void fold(v4d (&acc)[4][4], double pd, double pinv)
 // (fewer than 16 products fit below 2^53), else every fold_stages stages.
 // SPLIT: schedule for two waves per SIMD (see the loop).
 template <int WGM, int WGN, int NST, bool SPLIT, bool FINE>
-__device__ void f64_tile(const F64Job &J, int tm, int tn, char *smem, int split)
+__device__ __forceinline__ void f64_tile(const F64Job &J, int tm, int tn, char *smem, int split)
 {
     using C = F64Cfg<WGM, WGN, NST>;
     const int tid = threadIdx.x;

@@ -180,7 +180,7 @@ __device__ __forceinline__ void stage_schedule()
 // work runs (two fragment sets in registers), so the LDS reads that follow
 // every barrier no longer stall the matrix core.
 template <int SE, int TM, int TN, int WGM, int WGN, int KS, int NST, bool PIPE>
-__device__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
+__device__ __forceinline__ void i8_tile(const I8Job &J, int tm, int tn, char *smem)
 {
     using C = Cfg<SE, TM, TN, WGM, WGN, KS>;
     using F = Frags<SE, TM, TN, C::H>;

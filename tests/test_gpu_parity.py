@@ -126,6 +126,26 @@ def test_fp64_large_moduli_reduction_schedule(p):
     assert np.array_equal(got, oracle.fgemm(p, A, B, None, 1, 0))
 
 
+@pytest.mark.parametrize("p,opts", [(2147483647, dict(path=INT8, digit_bits=7)),
+                                     (2147483629, dict(path=INT8, digit_bits=8)),
+                                     (94906249, dict(path=FP64)),
+                                     (3, dict(path=FP64)), (2, dict(path=INT8, digit_bits=7))],
+                         ids=["p2^31-1-int8d7", "p2147483629-int8d8", "p94906249-fp64",
+                              "p3-fp64", "p2-int8d7"])
+def test_epilogue_products_at_the_largest_residues(p, opts):
+    # alpha, beta and C near p - 1: the epilogue's products mod p (alpha*r,
+    # beta*c) at their largest operands; then every residue p - 1
+    m, n, k = 70, 130, 190
+    A, B, C = inputs(p, m, n, k, 14)
+    alpha, beta = (p - 2) % p, (p - 3) % p
+    got = run(p, A, B, C, alpha, beta, **opts)
+    assert np.array_equal(got, oracle.fgemm(p, A, B, C, alpha, beta))
+    full = np.full((m, k), p - 1, np.uint32), np.full((k, n), p - 1, np.uint32)
+    Cf = np.full((m, n), p - 1, np.uint32)
+    got = run(p, full[0], full[1], Cf, p - 1, p - 1, **opts)
+    assert np.array_equal(got, oracle.fgemm(p, full[0], full[1], Cf, p - 1, p - 1))
+
+
 def test_int8_k_split_beyond_int32_block():
     # p = 251 direct plane: one int32 pass is exact up to k = 137438, so
     # k = 140000 takes two passes chained with beta = 1
