@@ -116,6 +116,28 @@ def test_plan_configs_of_the_workloads():
         assert i.kblock == kb
 
 
+def test_plan_fp64_tiles_and_split_k_workspace():
+    # FP64 products up to 1024 x 1024 take the 128 x 128 tile (id 2), larger
+    # ones the 256 x 128 tile (id 1).  A single launch with fewer than 128
+    # tiles splits K into min(K stages, 512 / tiles) parts; the workspace is
+    # the packed operands (8 bytes per padded element) plus, 256-aligned,
+    # one uint32 partial product per split.
+    o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0)
+    i = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096, o)
+    assert i.tile_config == 1
+    assert i.workspace_bytes == (4096 + 4096) * 4096 * 8          # 512 tiles: no split
+    i = ff.ff_plan_query(65521, 0, 0, 256, 256, 256, o)
+    assert i.tile_config == 2
+    tiles, stages = 4, 256 // 16
+    splits = min(stages, 512 // tiles)                              # 16 splits of 1 stage
+    assert i.workspace_bytes == (256 + 256) * 256 * 8 + 256 + splits * 256 * 256 * 4
+    i = ff.ff_plan_query(8388593, 0, 0, 3, 5, 1000003, o)
+    stages = (1000003 + 15) // 16
+    per = -(-stages // 512)
+    splits = -(-stages // per)
+    assert i.workspace_bytes == (128 + 128) * stages * 16 * 8 + 256 + splits * 3 * 5 * 4
+
+
 @pytest.mark.parametrize("args,msg", [
     ((1, 0, 0, 4, 4, 4, 1, 8, 4, 8, 4, 0, 8, 4), "p must"),
     ((7, 2, 0, 4, 4, 4, 1, 8, 4, 8, 4, 0, 8, 4), "trans"),

@@ -146,6 +146,17 @@ def test_epilogue_products_at_the_largest_residues(p, opts):
     assert np.array_equal(got, oracle.fgemm(p, full[0], full[1], Cf, p - 1, p - 1))
 
 
+@pytest.mark.parametrize("opts", PATHS, ids=["fp64", "int8d7", "int8d8"])
+def test_long_k_tiny_output(opts):
+    # k = 1000003 with a 3 x 5 output: FP64 splits K 512 ways with
+    # reductions inside every split; INT8 runs 8 (7-bit) or 23 (8-bit)
+    # int32 K-passes chained with beta = 1
+    p = 8388593
+    A, B, C = inputs(p, 3, 5, 1000003, 15)
+    got = run(p, A, B, C, 7, 11, **opts)
+    assert np.array_equal(got, oracle.fgemm(p, A, B, C, 7, 11))
+
+
 def test_int8_k_split_beyond_int32_block():
     # p = 251 direct plane: one int32 pass is exact up to k = 137438, so
     # k = 140000 takes two passes chained with beta = 1
