@@ -10,6 +10,8 @@ Contents
   ctypes wrappers around ``oracle.c`` (the plain definition of
   C <- alpha*A*B + beta*C mod p, Section 3; 128-bit accumulation with a
   reduction after every multiply-add).
+* ``ftrsm``: the triangular solve op(T) X = alpha B mod p of Section 4 by
+  plain substitution, every multiply-add reduced.
 * ``oracle.bounds``: the paper's accumulation and growth bounds (eq. (1),
   eq. (2), Theorem 3.1, Corollaries 3.2-3.4) in exact Python integers.
 * ``oracle.winograd``: Winograd's variant in exact Python integers (the
@@ -61,6 +63,9 @@ def _load(plant=None):
     lib.oracle_int_matmul.restype = _INT
     lib.oracle_crt.argtypes = [_INT, _u32p, _I64, _u32p, _u64p, _i64p]
     lib.oracle_crt.restype = _INT
+    lib.oracle_ftrsm.argtypes = [_U32, _INT, _INT, _INT, _I64, _I64, _U32, ctypes.c_void_p,
+                                 _I64, ctypes.c_void_p, _I64]
+    lib.oracle_ftrsm.restype = _INT
     _libs[key] = lib
     return lib
 
@@ -186,3 +191,21 @@ def crt(primes, residues):
     if rc != 0:
         raise ValueError("oracle_crt rejected its arguments")
     return lo.reshape(shape), hi.reshape(shape)
+
+
+def ftrsm(p, T, B, alpha=1, lower=False, trans=False, unit=False, plant=None):
+    """X with op(T) X = alpha B (mod p), T m x m triangular (upper unless
+    `lower`; op(T) = T^T if `trans`; `unit`: unit diagonal, not read), B m x n.
+    Returns X (a new array).  Raises ZeroDivisionError when a diagonal entry
+    has no inverse modulo p."""
+    T = np.ascontiguousarray(T, dtype=np.uint32)
+    X = np.array(B, dtype=np.uint32, order="C", copy=True)
+    m, n = X.shape
+    assert T.shape == (m, m)
+    rc = _load(plant).oracle_ftrsm(p, int(lower), int(trans), int(unit), m, n, alpha,
+                                    _ptr(T), max(m, 1), _ptr(X), max(n, 1))
+    if rc == -2:
+        raise ZeroDivisionError("a diagonal entry of T is not invertible modulo p")
+    if rc != 0:
+        raise ValueError("oracle_ftrsm rejected its arguments")
+    return X

@@ -198,3 +198,52 @@ def winograd_leaf_operand_range(loA, hiA, loB, hiB, l):
         lo = min(lo, la, lb)
         hi = max(hi, ha, hb)
     return lo, hi
+
+
+# --- Section 4.2, delayed reductions in a triangular solve -----------------
+
+def trsm_uv(m, M, k):
+    """Theorem 4.2: u_k and v_k for a unit upper triangular system whose
+    entries (and right-hand side) lie in [m, M], m <= 0 <= M.  The unknown
+    x_{n-k} lies in [-u_k, v_k] for even k and [-v_k, u_k] for odd k.
+    Returned as exact rationals (the halves cancel for integer inputs of the
+    same parity)."""
+    u = Fraction(M - m, 2) * (M + 1) ** k - Fraction(M + m, 2) * (M - 1) ** k
+    v = Fraction(M - m, 2) * (M + 1) ** k + Fraction(M + m, 2) * (M - 1) ** k
+    return u, v
+
+
+def trsm_bound(m, M, n):
+    """Corollary 4.3: |x| <= v_{n-1} for a system of dimension n."""
+    return trsm_uv(m, M, n - 1)[1]
+
+
+def trsm_bound_positive(p, n):
+    """Corollary 4.4: entries in [0, p-1]."""
+    return Fraction(p - 1, 2) * (p ** (n - 1) + (p - 1) ** (n - 1))
+
+
+def trsm_bound_balanced(p, n):
+    """Corollary 4.5: entries in [-(p-1)/2, (p-1)/2]."""
+    return Fraction(p - 1, 2) * Fraction(p + 1, 2) ** (n - 1)
+
+
+def t_del_positive(p, gamma=53):
+    """eq. (trsmboundpos): the largest n with (p-1)/2 (p^(n-1) + (p-1)^(n-1))
+    < 2^gamma, the dimension of a unit triangular solve over Z that needs no
+    reduction (positive representation)."""
+    n = 1
+    while trsm_bound_positive(p, n + 1) < (1 << gamma):
+        n += 1
+    return n
+
+
+def t_del_balanced(p, gamma=53):
+    """eq. (trsmboundcen) as printed: the largest n with
+    (p-1)/2 ((p+1)/2)^n < 2^gamma.  The exponent is n where Corollary 4.5
+    has n - 1 (reading: the printed, more conservative form, which gives the
+    text's 52 for p = 3)."""
+    n = 0
+    while Fraction(p - 1, 2) * Fraction(p + 1, 2) ** (n + 1) < (1 << gamma):
+        n += 1
+    return n

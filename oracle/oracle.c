@@ -238,3 +238,63 @@ int oracle_crt(int nprime, const uint32_t *primes, int64_t count,
     }
     return 0;
 }
+
+/*
+ * Triangular system with matrix right-hand side (Section 4): X such that
+ *     op(T) X = alpha B   (mod p),
+ * T m x m triangular (uplo 0: upper, 1: lower; trans 1: op(T) = T^T; diag 1:
+ * unit diagonal, the stored diagonal is not read), B m x n, overwritten by X.
+ * Plain substitution, row by row in the order the triangle allows, every
+ * multiply-add reduced:
+ *     x_i = (alpha b_i - sum_{l solved} op(T)_il x_l) * op(T)_ii^(-1)  mod p.
+ * The inverse comes from the extended Euclidean algorithm, so any modulus
+ * works as long as the diagonal entries are units.  Columns of B are
+ * independent (OpenMP over them).  Returns 0, -1 on a bad argument, -2 when a
+ * diagonal entry has no inverse modulo p.
+ */
+static int64_t inv_euclid(uint64_t a, uint64_t p)
+{
+    int64_t r0 = (int64_t)p, r1 = (int64_t)(a % p), s0 = 0, s1 = 1;
+    while (r1 != 0) {
+        const int64_t q = r0 / r1, r2 = r0 - q * r1, s2 = s0 - q * s1;
+        r0 = r1; r1 = r2; s0 = s1; s1 = s2;
+    }
+    if (r0 != 1) return -1;
+    return s0 < 0 ? s0 + (int64_t)p : s0;
+}
+
+int oracle_ftrsm(uint32_t p, int uplo, int trans, int diag, int64_t m, int64_t n,
+                 uint32_t alpha, const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb)
+{
+    if (p < 2 || m < 0 || n < 0) return -1;
+    if ((uplo != 0 && uplo != 1) || (trans != 0 && trans != 1) || (diag != 0 && diag != 1))
+        return -1;
+    if (m == 0 || n == 0) return 0;
+    if (ldt < m || ldb < n) return -1;
+    const u128 P = p;
+    /* op(T) is lower triangular when exactly one of (lower, transposed) holds */
+    const int lower = uplo ^ trans;
+    int64_t bad = 0;
+    if (!diag) {
+        for (int64_t i = 0; i < m; ++i)
+            if (inv_euclid(T[i * ldt + i], p) < 0) bad = 1;
+        if (bad) return -2;
+    }
+    const u128 al = alpha % p;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t s = 0; s < m; ++s) {
+            const int64_t i = lower ? s : m - 1 - s;
+            u128 acc = (al * B[i * ldb + j]) % P;
+            for (int64_t t = 0; t < s; ++t) {
+                const int64_t l = lower ? t : m - 1 - t;
+                const u128 til = op_elem(T, ldt, trans, i, l) % P;
+                acc = (acc + (P - til) * B[l * ldb + j]) % P;
+            }
+            if (!diag && !PLANT(6)) /* planted: diagonal division skipped */
+                acc = (acc * (u128)inv_euclid(op_elem(T, ldt, trans, i, i), p)) % P;
+            B[i * ldb + j] = (uint32_t)acc;
+        }
+    }
+    return 0;
+}
