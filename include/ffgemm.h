@@ -62,6 +62,8 @@ typedef enum {
 } ff_status;
 
 enum { FF_NOTRANS = 0, FF_TRANS = 1 };
+enum { FF_UPPER = 0, FF_LOWER = 1 };   /* triangle of T that ff_ftrsm reads  */
+enum { FF_NONUNIT = 0, FF_UNIT = 1 };  /* diagonal of T: stored, or all ones */
 
 /* Arithmetic path.  FP64: centered residues as doubles on FP64 matrix
  * cores, reduction every kblock products (Section 2.1.2, eq. (2), read with
@@ -141,6 +143,32 @@ int ff_fgemm_ex(uint32_t p, int transA, int transB,
                 uint32_t alpha, const uint32_t *A, int64_t lda,
                 const uint32_t *B, int64_t ldb,
                 uint32_t beta, uint32_t *C, int64_t ldc,
+                const ff_opts *opts);
+
+/* Triangular system with matrix right-hand side (Section 4):
+ *
+ *     B <- X  with  op(T) X = alpha B   (mod p).
+ *
+ * T is m x m with leading dimension ldt >= m; only the triangle named by
+ * uplo (FF_UPPER or FF_LOWER) is read, and with diag == FF_UNIT not its
+ * diagonal either (taken as ones).  op(T) = T (FF_NOTRANS) or T^T
+ * (FF_TRANS).  B is m x n with ldb >= n and is overwritten by X; T and B
+ * are device pointers owned by the caller and must not overlap.  With
+ * FF_NONUNIT every diagonal entry must be invertible modulo p (any unit
+ * when p is prime): otherwise the result is unspecified, unless
+ * opts->validate is set, which checks B's entries and T's diagonal first
+ * (synchronously) and returns FF_EINVAL without writing.  The solve is the
+ * block recursive algorithm of Section 4.1 on the unit triangular system
+ * D^-1 op(T) X = alpha D^-1 B of Section 4.2 (D the diagonal of op(T));
+ * its updates are fgemm calls that follow opts->path.  m == 0 or n == 0
+ * does nothing; alpha == 0 (mod p) gives B <- 0.  Workspace: 4 m^2 bytes
+ * held by the library per stream, besides the fgemm workspace. */
+int ff_ftrsm(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n,
+             uint32_t alpha, const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb);
+
+/* Same, with explicit options (NULL opts = automatic). */
+int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n,
+                uint32_t alpha, const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb,
                 const ff_opts *opts);
 
 /* The plan ff_fgemm_ex would follow for these sizes (host-only). */

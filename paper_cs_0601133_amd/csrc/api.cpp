@@ -40,7 +40,7 @@ struct DevState {
     bool checked = false;
     bool ok = false;
     std::string arch;
-    std::map<hipStream_t, Buffer> ws;
+    std::map<std::pair<hipStream_t, int>, Buffer> ws; // (stream, slot)
     std::map<hipStream_t, unsigned *> ctr;
     struct Staging {
         void *host = nullptr; // pinned
@@ -85,7 +85,7 @@ int check_device()
 // Grow-only workspace per (device, stream).  Calls on one stream run in
 // order, so reusing its workspace is safe; before a buffer is replaced the
 // stream is drained.
-int workspace(hipStream_t st, size_t bytes, void **out)
+int workspace(hipStream_t st, size_t bytes, void **out, int slot)
 {
     int dev = 0;
     FF_HIP_CHECK(hipGetDevice(&dev));
@@ -95,7 +95,7 @@ int workspace(hipStream_t st, size_t bytes, void **out)
         ds = g_devs[dev];
     }
     std::lock_guard<std::mutex> lk(ds->mu);
-    Buffer &b = ds->ws[st];
+    Buffer &b = ds->ws[{st, slot}];
     if (b.bytes < bytes) {
         if (b.ptr) {
             FF_HIP_CHECK(hipStreamSynchronize(st));
@@ -177,7 +177,7 @@ int release_all()
         std::lock_guard<std::mutex> lk2(ds->mu);
         for (auto &w : ds->ws) {
             if (w.second.ptr) {
-                (void)hipStreamSynchronize(w.first);
+                (void)hipStreamSynchronize(w.first.first);
                 (void)hipFree(w.second.ptr);
             }
         }

@@ -204,6 +204,25 @@ hipError_t launch_i8_batched(int tile, const I8Job *dev_jobs, int njobs,
                              int total_tiles, int persistent, unsigned *ctr,
                              hipStream_t st);
 
+// Triangular solve (kernels_trsm.hip): rows per diagonal block.
+constexpr int TRSM_BS = 64;
+// dinv_i = op(T)_ii^-1 mod p (1 when unit), *bad counts diagonal entries with
+// no inverse.
+hipError_t launch_trsm_dinv(const uint32_t *T, int64_t ldt, int64_t m, uint32_t p, int unit,
+                            uint32_t *dinv, unsigned *bad, hipStream_t st);
+// Tn = D^-1 op(T) restricted to its triangle (lower: op(T) lower), unit
+// diagonal, zero elsewhere; m x m row-major.
+hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower, int64_t m,
+                            uint32_t p, const uint32_t *dinv, uint32_t *Tn, hipStream_t st);
+// B(i, :) <- alpha dinv_i B(i, :) mod p.
+hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uint32_t p,
+                             uint32_t alpha, const uint32_t *dinv, hipStream_t st);
+// Solves rows [r0, r0 + bs) of Tn X = B in place (bs <= TRSM_BS); exact:
+// binary64 dot products are exact (TRSM_BS (p/2)^2 + p/2 <= 2^53).
+hipError_t launch_trsm_diag(const uint32_t *Tn, int64_t m, int lower, int64_t r0, int bs,
+                            uint32_t *B, int64_t ldb, int64_t n, uint32_t p, int exact,
+                            hipStream_t st);
+
 // C <- (alpha * sum_s part[s] + beta*C) mod p over nsplit partial products
 // part[s][m][n] in [0, p).
 hipError_t launch_split_reduce(const uint32_t *part, int nsplit, int64_t m, int64_t n,

@@ -7,7 +7,10 @@
 namespace ff {
 
 int check_device();
-int workspace(hipStream_t st, size_t bytes, void **out);
+// Per-(device, stream, slot) device buffer, grown on demand (growth waits
+// for the stream).  Slot 0 serves fgemm; a routine that calls fgemm while
+// holding data of its own (the triangular solve) uses slot 1.
+int workspace(hipStream_t st, size_t bytes, void **out, int slot = 0);
 // 256-byte zeroed counter block per (device, stream) for persistent kernels,
 // which leave it zeroed.
 int counter_buffer(hipStream_t st, unsigned **out);

@@ -1,0 +1,157 @@
+// Triangular system with matrix right-hand side over Z/pZ (Section 4):
+// B <- X with op(T) X = alpha B (mod p).
+//
+// Normalisation (Section 4.2): with D the diagonal of op(T), T' = D^-1 op(T)
+// has a unit diagonal and T' X = alpha D^-1 B involves ring operations only.
+// The solve is the block recursive algorithm of Section 4.1: split the rows
+// in two, solve the part the triangle allows first, subtract its
+// contribution from the other part with one fgemm (C <- C - A X, reduced in
+// the GEMM epilogue), solve the other part.  The recursion stops at
+// diagonal blocks of TRSM_BS rows, solved one column per thread with
+// products summed exactly in binary64 and one reduction per unknown.
+//
+// The paper's cascades (blocks of t_del rows solved over Z by a numerical
+// trsm, updates left unreduced below t_update) save reduction passes around
+// CPU BLAS calls; here the reduction of an update is fused into the fgemm
+// epilogue and the diagonal kernel reduces each unknown once, so the
+// recursion reduces at every level at no extra pass.
+#include <algorithm>
+#include <cstring>
+
+#include "ff_profile.h"
+#include "ff_runtime.h"
+
+namespace ff {
+
+namespace {
+
+struct Trsm {
+    uint32_t p;
+    int lower; // op(T) lower triangular
+    int64_t m, n;
+    const uint32_t *Tn;
+    uint32_t *B;
+    int64_t ldb;
+    int exact;
+    ff_opts o; // inner fgemm options (stream set, no validation)
+    hipStream_t st;
+};
+
+int solve(const Trsm &c, int64_t r0, int64_t r1)
+{
+    const int64_t size = r1 - r0;
+    if (size <= TRSM_BS) {
+        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, c.st,
+                              launch_trsm_diag(c.Tn, c.m, c.lower, r0, (int)size, c.B, c.ldb,
+                                               c.n, c.p, c.exact, c.st)));
+        return FF_OK;
+    }
+    // split at a multiple of the block size near the middle
+    const int64_t mid = r0 + round_up(size / 2, TRSM_BS);
+    const uint32_t minus1 = c.p - 1;
+    int rc;
+    if (!c.lower) {
+        // upper: rows [mid, r1) first, then B[r0:mid] -= T'[r0:mid, mid:r1] X[mid:r1]
+        if ((rc = solve(c, mid, r1))) return rc;
+        if ((rc = ff_fgemm_ex(c.p, 0, 0, mid - r0, c.n, r1 - mid, minus1,
+                              c.Tn + r0 * c.m + mid, c.m, c.B + mid * c.ldb, c.ldb, 1,
+                              c.B + r0 * c.ldb, c.ldb, &c.o)))
+            return rc;
+        return solve(c, r0, mid);
+    }
+    // lower: rows [r0, mid) first, then B[mid:r1] -= T'[mid:r1, r0:mid] X[r0:mid]
+    if ((rc = solve(c, r0, mid))) return rc;
+    if ((rc = ff_fgemm_ex(c.p, 0, 0, r1 - mid, c.n, mid - r0, minus1, c.Tn + mid * c.m + r0,
+                          c.m, c.B + r0 * c.ldb, c.ldb, 1, c.B + mid * c.ldb, c.ldb, &c.o)))
+        return rc;
+    return solve(c, mid, r1);
+}
+
+} // namespace
+
+} // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n,
+                uint32_t alpha, const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb,
+                const ff_opts *opts)
+{
+    if (p < 2 || p > 0x7FFFFFFFu) return fail(FF_EINVAL, "p must be in [2, 2^31 - 1]");
+    if ((uplo != FF_UPPER && uplo != FF_LOWER) || (transT != FF_NOTRANS && transT != FF_TRANS) ||
+        (diag != FF_NONUNIT && diag != FF_UNIT))
+        return fail(FF_EINVAL, "uplo, transT and diag must be FF_UPPER/FF_LOWER, "
+                               "FF_NOTRANS/FF_TRANS and FF_NONUNIT/FF_UNIT");
+    if (m < 0 || n < 0) return fail(FF_EINVAL, "negative dimension");
+    if (m == 0 || n == 0) return FF_OK;
+    if (!T || !B) return fail(FF_EINVAL, "null matrix pointer");
+    if (ldt < m) return fail(FF_EINVAL, "ldt < m");
+    if (ldb < n) return fail(FF_EINVAL, "ldb < n");
+    if (m > 0x7FFFFFFF / 2) return fail(FF_EINVAL, "m too large");
+    ff_opts o = opts ? *opts : default_opts();
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = stream_of(&o);
+    alpha %= p;
+    if (o.validate) {
+        unsigned *bad = nullptr;
+        FF_HIP_CHECK(hipMalloc(&bad, sizeof(unsigned)));
+        unsigned h = 0;
+        hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned), st);
+        if (e == hipSuccess) e = launch_validate(B, ldb, m, n, p, bad, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(bad);
+        if (e != hipSuccess) return fail(FF_EHIP, std::string("validate: ") + hipGetErrorString(e));
+        if (h) return fail(FF_EINVAL, std::to_string(h) + " entries of B are not residues < p");
+    }
+    if (alpha == 0) { // X = 0
+        FF_HIP_CHECK(launch_scale(B, ldb, m, n, p, 0, st));
+        return FF_OK;
+    }
+    // workspace slot 1 (the inner fgemm calls use slot 0): T', dinv, a flag
+    const int64_t tn_bytes = round_up(m * m * 4, 256), di_bytes = round_up(m * 4, 256);
+    void *wsv = nullptr;
+    if ((rc = workspace(st, (size_t)(tn_bytes + di_bytes + 256), &wsv, 1))) return rc;
+    uint32_t *Tn = (uint32_t *)wsv;
+    uint32_t *dinv = (uint32_t *)((char *)wsv + tn_bytes);
+    unsigned *bad = (unsigned *)((char *)wsv + tn_bytes + di_bytes);
+    const int lower = (uplo == FF_LOWER) ^ (transT == FF_TRANS);
+    FF_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), st));
+    FF_HIP_CHECK(launch_trsm_dinv(T, ldt, m, p, diag == FF_UNIT, dinv, bad, st));
+    if (o.validate && diag != FF_UNIT) {
+        unsigned h = 0;
+        FF_HIP_CHECK(hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        FF_HIP_CHECK(hipStreamSynchronize(st));
+        if (h)
+            return fail(FF_EINVAL,
+                        std::to_string(h) + " diagonal entries of T have no inverse modulo p");
+    }
+    FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, p, dinv, Tn, st));
+    if (alpha != 1 || diag != FF_UNIT) FF_HIP_CHECK(launch_trsm_scale(B, ldb, m, n, p, alpha, dinv, st));
+    Trsm c;
+    c.p = p;
+    c.lower = lower;
+    c.m = m;
+    c.n = n;
+    c.Tn = Tn;
+    c.B = B;
+    c.ldb = ldb;
+    const double h = (double)(p / 2);
+    c.exact = (double)TRSM_BS * h * h + h <= 9007199254740992.0;
+    c.o = o;
+    c.o.stream = (void *)st;
+    c.o.validate = 0;
+    c.st = st;
+    return solve(c, 0, m);
+}
+
+int ff_ftrsm(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, uint32_t alpha,
+             const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb)
+{
+    return ff_ftrsm_ex(p, uplo, transT, diag, m, n, alpha, T, ldt, B, ldb, nullptr);
+}
+
+} // extern "C"

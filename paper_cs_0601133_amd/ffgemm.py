@@ -21,6 +21,10 @@ FF_ENOTFOUND = -6
 
 FF_NOTRANS = 0
 FF_TRANS = 1
+FF_UPPER = 0
+FF_LOWER = 1
+FF_NONUNIT = 0
+FF_UNIT = 1
 
 FF_PATH_AUTO = 0
 FF_PATH_FP64 = 1
@@ -62,6 +66,9 @@ _SIGS = {
                   _VP, _I64], _INT),
     "ff_fgemm_ex": ([_U32, _INT, _INT, _I64, _I64, _I64, _U32, _VP, _I64, _VP, _I64, _U32,
                      _VP, _I64, ctypes.POINTER(ff_opts)], _INT),
+    "ff_ftrsm": ([_U32, _INT, _INT, _INT, _I64, _I64, _U32, _VP, _I64, _VP, _I64], _INT),
+    "ff_ftrsm_ex": ([_U32, _INT, _INT, _INT, _I64, _I64, _U32, _VP, _I64, _VP, _I64,
+                     ctypes.POINTER(ff_opts)], _INT),
     "ff_plan_query": ([_U32, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ff_opts),
                        ctypes.POINTER(ff_plan_info)], _INT),
     "ff_fgemm_batched": ([ctypes.POINTER(ff_job), _INT, ctypes.POINTER(ff_opts)], _INT),
@@ -198,6 +205,16 @@ def ff_fgemm_ex(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                               ldb, beta, _addr(C), ldc, o)
 
 
+def ff_ftrsm(p, uplo, transT, diag, m, n, alpha, T, ldt, B, ldb):
+    return load().ff_ftrsm(p, uplo, transT, diag, m, n, alpha, _addr(T), ldt, _addr(B), ldb)
+
+
+def ff_ftrsm_ex(p, uplo, transT, diag, m, n, alpha, T, ldt, B, ldb, opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_ftrsm_ex(p, uplo, transT, diag, m, n, alpha, _addr(T), ldt, _addr(B), ldb,
+                              o)
+
+
 def ff_plan_query(p, transA, transB, m, n, k, opts=None):
     info = ff_plan_info()
     o = ctypes.byref(opts) if opts is not None else None
@@ -301,6 +318,18 @@ def job(p, A, B, C, alpha=1, beta=0, transA=False, transB=False):
     n = B.shape[0] if transB else B.shape[1]
     return ff_job(p, int(transA), int(transB), m, n, k, alpha % p, beta % p, _addr(A),
                   _ld(A, 1), _addr(B), _ld(B, 1), _addr(C), _ld(C, 1))
+
+
+def ftrsm(p, T, B, alpha=1, lower=False, trans=False, unit=False, opts=None):
+    """B <- X with op(T) X = alpha B (mod p) for torch tensors T (m x m) and B
+    (m x n), on torch's current stream."""
+    m, n = B.shape[0], B.shape[1]
+    if opts is None:
+        opts = make_opts()
+    if not opts.stream:
+        opts.stream = _torch_stream()
+    return _check(ff_ftrsm_ex(p, int(lower), int(trans), int(unit), m, n, alpha % p, T,
+                              _ld(T, 1), B, _ld(B, 1), opts))
 
 
 def fgemm(p, A, B, C, alpha=1, beta=0, transA=False, transB=False, opts=None):
