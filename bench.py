@@ -14,8 +14,9 @@ The JSON line also carries the roofline of the dominant kernel (the INT8
 digit GEMM, timed with HIP events around its launches), the CPU oracle timed
 on a bounded sample of the same product, and the other workloads: the
 n = 256 latency case, n = 8192 at p = 251 and with Winograd levels, the
-64-job multi-modular batch (plain, persistent and graph-replayed) and the
-Poisson serving stream.
+64-job multi-modular batch (plain, persistent and graph-replayed), the
+triangular solve with matrix right-hand side (Section 4) and the Poisson
+serving stream.
 """
 import argparse
 import hashlib
@@ -284,6 +285,32 @@ def multimodular(torch, ff, args):
     return out
 
 
+def triangular_solve(torch, ff, args):
+    """ftrsm: op(T) X = 3 B mod p, T lower triangular m x m with an invertible
+    diagonal, B m x n, solved in place on the path the planner picks for
+    the updates (a repeated solve on its own output costs the same).
+    Throughput is m^2 n / t: m(m - 1)n/2 multiply-adds, each counted as a
+    multiplication and an addition, like 2mnk for a product."""
+    from paper_cs_0601133_amd import synth
+    out = {}
+    for m, n, p in ((4096, 4096, 8388593), (4096, 4096, 65521), (4096, 4096, 2147483647),
+                    (8192, 8192, 8388593)):
+        T = synth.residues(0x5EED0000 + 7000 + m, (m, m), p)
+        d = np.arange(m)
+        T[d, d] = 1 + T[d, d] % (p - 1)
+        B = synth.residues(0x5EED0000 + 7001 + m, (m, n), p)
+        dT = torch.from_numpy(T.view(np.int32)).cuda()
+        dB = torch.from_numpy(B.view(np.int32)).cuda()
+        del T, B
+        ms, per, _ = time_calls(torch, lambda: ff.ftrsm(p, dT, dB, 3, lower=True), 5, 2)
+        med = float(np.median(per))
+        out[f"m{m}_n{n}_p{p}"] = {"ms": ms, "ms_median_events": med,
+                                   "gops_m2n": m * m * n / ms / 1e6}
+        log(f"ftrsm m={m} n={n} p={p}: {ms:.3f} ms")
+        del dT, dB
+    return out
+
+
 def serving(torch, ff, args):
     nreq = args.serve_requests
     rng = np.random.default_rng(5)
@@ -390,6 +417,7 @@ def main():
             "n256_p65521_latency": small_latency(torch, ff, args),
             "n8192": large_8192(torch, ff, args),
             "multimodular_64_jobs": multimodular(torch, ff, args),
+            "ftrsm": triangular_solve(torch, ff, args),
             "serving": serving(torch, ff, args),
         }
     if not args.no_cpu:

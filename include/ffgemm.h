@@ -160,9 +160,12 @@ int ff_fgemm_ex(uint32_t p, int transA, int transB,
  * (synchronously) and returns FF_EINVAL without writing.  The solve is the
  * block recursive algorithm of Section 4.1 on the unit triangular system
  * D^-1 op(T) X = alpha D^-1 B of Section 4.2 (D the diagonal of op(T));
- * its updates are fgemm calls that follow opts->path.  m == 0 or n == 0
- * does nothing; alpha == 0 (mod p) gives B <- 0.  Workspace: 4 m^2 bytes
- * held by the library per stream, besides the fgemm workspace. */
+ * its updates are fgemm calls that follow opts->path, and its leaves (up
+ * to 512 rows) are solved on the device with the inverses of the 64 x 64
+ * diagonal blocks, exactly for every p.  m == 0 or n == 0 does nothing;
+ * alpha == 0 (mod p) gives B <- 0.  Workspace: 4 mp^2 + 256 mp bytes
+ * (mp = m rounded up to a multiple of 64) held by the library per stream,
+ * besides the fgemm workspace. */
 int ff_ftrsm(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n,
              uint32_t alpha, const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb);
 

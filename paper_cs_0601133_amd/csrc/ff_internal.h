@@ -204,24 +204,33 @@ hipError_t launch_i8_batched(int tile, const I8Job *dev_jobs, int njobs,
                              int total_tiles, int persistent, unsigned *ctr,
                              hipStream_t st);
 
-// Triangular solve (kernels_trsm.hip): rows per diagonal block.
-constexpr int TRSM_BS = 64;
+// Triangular solve (kernels_trsm.hip): the block recursion stops at leaves
+// of at most TRSM_LEAF_MAX rows (a multiple of 64), solved by one kernel.
+constexpr int TRSM_LEAF_MAX = 512;
 // dinv_i = op(T)_ii^-1 mod p (1 when unit), *bad counts diagonal entries with
 // no inverse.
 hipError_t launch_trsm_dinv(const uint32_t *T, int64_t ldt, int64_t m, uint32_t p, int unit,
                             uint32_t *dinv, unsigned *bad, hipStream_t st);
 // Tn = D^-1 op(T) restricted to its triangle (lower: op(T) lower), unit
-// diagonal, zero elsewhere; m x m row-major.
+// diagonal, zero elsewhere; ldn x ldn row-major (ldn = m rounded up to a
+// multiple of 64, padding = identity).
 hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower, int64_t m,
-                            uint32_t p, const uint32_t *dinv, uint32_t *Tn, hipStream_t st);
+                            int64_t ldn, uint32_t p, const uint32_t *dinv, uint32_t *Tn,
+                            hipStream_t st);
 // B(i, :) <- alpha dinv_i B(i, :) mod p.
 hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uint32_t p,
                              uint32_t alpha, const uint32_t *dinv, hipStream_t st);
-// Solves rows [r0, r0 + bs) of Tn X = B in place (bs <= TRSM_BS); exact:
-// binary64 dot products are exact (TRSM_BS (p/2)^2 + p/2 <= 2^53).
-hipError_t launch_trsm_diag(const uint32_t *Tn, int64_t m, int lower, int64_t r0, int bs,
-                            uint32_t *B, int64_t ldb, int64_t n, uint32_t p, int exact,
-                            hipStream_t st);
+// Tinv[g] = inverse of the 64 x 64 diagonal block g of Tn, g < ldn / 64
+// (64 x 64 row-major each); split as for the leaf.
+hipError_t launch_trsm_inv(const uint32_t *Tn, int64_t ldn, int lower, uint32_t p, int split,
+                           uint32_t *Tinv, hipStream_t st);
+// Solves rows [r0, r0 + rows) of Tn X = B in place, every other row's
+// contribution already subtracted; r0 a multiple of 64, rows <=
+// TRSM_LEAF_MAX.  split: operands cut in two (needed once
+// 64 (p/2)(p/2 + 2) + p/2 + 2 > 2^53).
+hipError_t launch_trsm_leaf(const uint32_t *Tn, int64_t ldn, const uint32_t *Tinv, int lower,
+                            int64_t r0, int rows, uint32_t *B, int64_t ldb, int64_t m, int64_t n,
+                            uint32_t p, int split, hipStream_t st);
 
 // C <- (alpha * sum_s part[s] + beta*C) mod p over nsplit partial products
 // part[s][m][n] in [0, p).

@@ -2,17 +2,21 @@
 //
 // The solve runs on a normalised copy T' = D^-1 op(T) with unit diagonal (D
 // the diagonal of op(T)): the system T' X = alpha D^-1 B involves ring
-// operations only (Section 4.2), so the products can be summed over Z with
-// reductions delayed.  Three element-wise passes prepare it (diagonal
-// inverses, T', the scaled right-hand side) and one kernel solves a
-// diagonal block of at most 64 rows for all columns of B; the updates
-// between diagonal blocks are fgemm calls (trsm.cpp).
+// operations only (Section 4.2).  Element-wise passes prepare it (diagonal
+// inverses, T', the scaled right-hand side), one kernel inverts every 64 x 64
+// diagonal block of T', and one kernel solves a leaf of the block recursion
+// (at most TRSM_LEAF_MAX rows) for a strip of 16 columns of B; the updates
+// between leaves are fgemm calls (trsm.cpp).
+#include <algorithm>
+
 #include "ff_device.h"
 #include "ff_internal.h"
 
 namespace ff {
 
 namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int TT = 256;
 
@@ -50,114 +54,369 @@ __global__ __launch_bounds__(TT) void k_trsm_dinv(const uint32_t *T, int64_t ldt
     dinv[i] = d;
 }
 
-// T'(i, j) = dinv_i op(T)(i, j) inside the triangle, 1 on the diagonal, 0
-// elsewhere; row-major with leading dimension m.
+// T'(i, j) = dinv_i op(T)(i, j) inside the triangle (i, j < m), 1 on the
+// whole diagonal, 0 elsewhere; ldn x ldn row-major, ldn = m rounded up to a
+// multiple of 64, so that every 64-row block is whole and its padding rows
+// and columns are those of the identity.  One workgroup per 64 x 64 tile:
+// tiles outside the triangle are written as zeros without reading T, and
+// op(T) = T^T goes through LDS so that both the reads and the writes run
+// along rows.
 __global__ __launch_bounds__(TT) void k_trsm_prep(const uint32_t *T, int64_t ldt, int trans,
-                                                  int lower, int64_t m, uint32_t p, double pinv,
-                                                  const uint32_t *dinv, uint32_t *Tn)
+                                                  int lower, int64_t m, int64_t ldn, uint32_t p,
+                                                  double pinv, const uint32_t *dinv,
+                                                  uint32_t *Tn)
 {
-    const int64_t total = m * m;
-    for (int64_t e = (int64_t)blockIdx.x * TT + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * TT) {
-        const int64_t i = e / m, j = e - i * m;
+    __shared__ uint32_t tile[64][65];
+    const int64_t nt = ldn / 64;
+    const int64_t ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    const int c = threadIdx.x & 63, r4 = threadIdx.x >> 6;
+    const int64_t i0 = 64 * ti, j0 = 64 * tj;
+    uint32_t *dst = Tn + i0 * ldn + j0;
+    if (lower ? tj > ti : tj < ti) {
+        for (int r = r4; r < 64; r += 4) dst[(int64_t)r * ldn + c] = 0u;
+        return;
+    }
+    // op(T)(i0 + r, j0 + c) into tile[r][c]
+    for (int r = r4; r < 64; r += 4) {
+        uint32_t v = 0;
+        if (trans) {
+            // read T(j0 + r, i0 + c) along the row, store transposed
+            if (j0 + r < m && i0 + c < m) v = T[(j0 + r) * ldt + i0 + c];
+            tile[c][r] = v;
+        } else {
+            if (i0 + r < m && j0 + c < m) v = T[(i0 + r) * ldt + j0 + c];
+            tile[r][c] = v;
+        }
+    }
+    __syncthreads();
+    for (int r = r4; r < 64; r += 4) {
+        const int64_t i = i0 + r, j = j0 + c;
         uint32_t v = 0;
         if (i == j) v = 1;
-        else if (lower ? j < i : j > i) v = mulmod(dinv[i], op_t(T, ldt, trans, i, j), p, pinv);
-        Tn[e] = v;
+        else if (i < m && j < m && (lower ? j < i : j > i)) v = mulmod(dinv[i], tile[r][c], p, pinv);
+        dst[(int64_t)r * ldn + c] = v;
     }
 }
 
-// B(i, j) <- alpha dinv_i B(i, j) mod p.
+// B(i, j) <- alpha dinv_i B(i, j) mod p: workgroup (x, y) scales 1024
+// columns of rows y, y + gridDim.y, ...
 __global__ __launch_bounds__(TT) void k_trsm_scale(uint32_t *B, int64_t ldb, int64_t m,
                                                    int64_t n, uint32_t p, double pinv,
                                                    uint32_t alpha, const uint32_t *dinv)
 {
-    const int64_t total = m * n;
-    for (int64_t e = (int64_t)blockIdx.x * TT + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * TT) {
-        const int64_t i = e / n, j = e - i * n;
-        uint32_t *bp = B + i * ldb + j;
-        *bp = mulmod(mulmod(alpha, dinv[i], p, pinv), *bp, p, pinv);
+    const int64_t j0 = (int64_t)blockIdx.x * 4 * TT + threadIdx.x;
+    for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
+        const uint32_t f = mulmod(alpha, dinv[i], p, pinv);
+        uint32_t *row = B + i * ldb;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + u * TT;
+            if (j < n) row[j] = mulmod(f, row[j], p, pinv);
+        }
     }
 }
 
-// Diagonal block: rows [r0, r0 + bs) of the unit triangular system T' X = B,
-// bs <= TRSM_BS, every other row's contribution already subtracted.  One
-// thread per column of B holds the block's column in registers and
-// substitutes in the triangle's order (forward for lower, backward for
-// upper); the block of T' sits in LDS and every lane reads the same word.
-// EXACT: values centered in binary64, x_i = r(b_i - sum_l t_il x_l) with one
-// reduction r per row, exact while TRSM_BS (p/2)^2 + p/2 <= 2^53 (the
-// delayed reduction of Section 2.1.2 on the substitution's dot products);
-// otherwise 32-bit residues and a reduction per product.  Rows past bs are
-// zero in registers and in LDS and do not change the others.
-template <bool EXACT>
-__global__ __launch_bounds__(TT) void k_trsm_diag(const uint32_t *Tn, int64_t m, int lower,
-                                                  int64_t r0, int bs, uint32_t *B, int64_t ldb,
-                                                  int64_t n, uint32_t p, double pinv)
+// x - p rint(x / p) for an integer-valued x, |x| <= 2^53: |result| <= p/2 + 2.
+__device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 {
-    constexpr int BS = TRSM_BS;
-    __shared__ double sT[EXACT ? BS * BS : 1];
-    __shared__ uint32_t sU[EXACT ? 1 : BS * BS];
+    return __builtin_fma(-__builtin_rint(x * pinv), pd, x);
+}
+
+// Inverse Y of the unit triangular diagonal block g of T' (rows and columns
+// [64g, 64g + 64)), written to Tinv + 4096 g (64 x 64 row-major).  Column j
+// of Y solves T' y = e_j; in the triangle's order (lower: l = 0, 1, ..;
+// upper: l = 63, 62, ..) y_l is final once the rows before it have been
+// subtracted, and is then subtracted, times T'(i, l), from every other row
+// (T' is read with its diagonal set to 0, and it is 0 on the far side of the
+// triangle, so no row needs a test).  A workgroup takes 16 columns of one
+// block; a thread keeps rows (tid / 16) + 16 r, r < 4, of its column in
+// registers, unreduced: each is a sum of at most 63 products of centered
+// values, exact in binary64 under the bound of the leaf solve (SPLIT: the
+// entries of T' cut in two as there).  The owner of row l publishes it,
+// reduced, through a two-slot LDS row, one barrier per step.
+template <bool SPLIT>
+__global__ __launch_bounds__(TT) void k_trsm_inv(const uint32_t *Tn, int64_t ldn, int lower,
+                                                 uint32_t p, double pinv, uint32_t *Tinv)
+{
+    __shared__ double sT[SPLIT ? 2 : 1][64][64]; // sT[.][l][i] = T'(i, l), diagonal 0
+    __shared__ double sRow[2][16];
+    const int g = blockIdx.x >> 2, jq = blockIdx.x & 3;
+    const int jl = threadIdx.x & 15, il = threadIdx.x >> 4;
+    const int j = 16 * jq + jl;
     const uint32_t half = (p - 1) / 2;
     const double pd = (double)p;
-    for (int e = threadIdx.x; e < BS * BS; e += TT) {
-        const int i = e / BS, l = e % BS;
-        const bool in = i < bs && l < bs && (lower ? l < i : l > i);
-        const uint32_t t = in ? Tn[(r0 + i) * m + r0 + l] : 0u;
-        if (EXACT) sT[e] = (double)center(t, p, half);
-        else sU[e] = t ? p - t : 0u; // -t mod p
+    const uint32_t *src = Tn + (int64_t)64 * g * ldn + 64 * g;
+    for (int e = threadIdx.x; e < 64 * 64; e += TT) {
+        const int i = e >> 6, l = e & 63;
+        const double t = i == l ? 0.0 : (double)center(src[(int64_t)i * ldn + l], p, half);
+        if (SPLIT) {
+            const double th = __builtin_rint(t * (1.0 / 32768.0));
+            sT[0][l][i] = th;
+            sT[SPLIT ? 1 : 0][l][i] = __builtin_fma(-th, 32768.0, t);
+        } else {
+            sT[0][l][i] = t;
+        }
+    }
+    double y[4], yh[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        y[r] = il + 16 * r == j ? 1.0 : 0.0;
+        yh[r] = 0.0;
     }
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * TT + threadIdx.x;
-    if (j >= n) return;
-    uint32_t *col = B + r0 * ldb + j;
-    if (EXACT) {
-        double x[BS];
+    for (int s = 0; s < 64; ++s) {
+        const int l = lower ? s : 63 - s;
+        if (il == (l & 15)) {
 #pragma unroll
-        for (int i = 0; i < BS; ++i)
-            x[i] = i < bs ? (double)center(col[(int64_t)i * ldb], p, half) : 0.0;
-#pragma unroll
-        for (int s = 0; s < BS; ++s) {
-            const int i = lower ? s : BS - 1 - s;
-            double acc = x[i];
-#pragma unroll
-            for (int t = 0; t < s; ++t) {
-                const int l = lower ? t : BS - 1 - t;
-                acc = __builtin_fma(-sT[i * BS + l], x[l], acc);
-            }
-            x[i] = __builtin_fma(-__builtin_rint(acc * pinv), pd, acc); // |x_i| <= p/2 + 1
+            for (int r = 0; r < 4; ++r)
+                if (r == (l >> 4)) {
+                    double v = y[r];
+                    if (SPLIT) v = __builtin_fma(reduce_c(yh[r], pd, pinv), 32768.0, v);
+                    v = reduce_c(v, pd, pinv);
+                    y[r] = v;
+                    yh[r] = 0.0;
+                    sRow[s & 1][jl] = v;
+                }
         }
+        __syncthreads();
+        const double yl = sRow[s & 1][jl];
 #pragma unroll
-        for (int i = 0; i < BS; ++i)
-            if (i < bs) col[(int64_t)i * ldb] = canon_f64(x[i], pd, pinv, p);
-    } else {
-        uint32_t x[BS];
-#pragma unroll
-        for (int i = 0; i < BS; ++i) x[i] = i < bs ? col[(int64_t)i * ldb] : 0u;
-#pragma unroll
-        for (int s = 0; s < BS; ++s) {
-            const int i = lower ? s : BS - 1 - s;
-            uint32_t acc = x[i];
-#pragma unroll
-            for (int t = 0; t < s; ++t) {
-                const int l = lower ? t : BS - 1 - t;
-                acc = addmod(acc, mulmod(sU[i * BS + l], x[l], p, pinv), p);
+        for (int r = 0; r < 4; ++r) {
+            const int i = il + 16 * r;
+            if (SPLIT) {
+                yh[r] = __builtin_fma(-sT[0][l][i], yl, yh[r]);
+                y[r] = __builtin_fma(-sT[SPLIT ? 1 : 0][l][i], yl, y[r]);
+            } else {
+                y[r] = __builtin_fma(-sT[0][l][i], yl, y[r]);
             }
-            x[i] = acc;
         }
+    }
+    // every row was reduced when it was published (its later updates add
+    // T'(i, l) = 0 terms only)
+    uint32_t *dst = Tinv + (int64_t)4096 * g;
 #pragma unroll
-        for (int i = 0; i < BS; ++i)
-            if (i < bs) col[(int64_t)i * ldb] = x[i];
+    for (int r = 0; r < 4; ++r) dst[(il + 16 * r) * 64 + j] = canon_f64(y[r], pd, pinv, p);
+}
+
+// ---------------------------------------------------------------------------
+// Leaf solve on the FP64 matrix cores.
+//
+// A workgroup owns 16 columns of B and walks the leaf's 64-row sub-blocks in
+// the triangle's order (lower: top down, upper: bottom up).  For sub-block b
+// it forms the residual
+//     R_b = B_b - sum_{q solved} T'_{bq} X_q           (reduced after every q)
+// with v_mfma_f64_16x16x4, then X_b = inv(T'_bb) R_b, one more 64-deep
+// product through LDS.  Values are centered residues in binary64: a sum of
+// at most 64 products stays an exact integer while
+// 64 (p/2)(p/2 + 2) + p/2 + 2 <= 2^53 (the delayed reduction of Section
+// 2.1.2); beyond that (SPLIT) each T' entry t is cut into t_hi 2^15 + t_lo
+// (|t_lo| <= 2^14) and the two sums, each below 2^51, are reduced
+// separately.
+//
+// Eight waves: wave (g, h) = (w % 4, w / 4) owns rows 16g .. 16g + 15 of the
+// sub-block and half h of every product's 64-deep sum, so two waves share a
+// SIMD and one's conversions overlap the other's matrix-core steps (with one
+// wave per SIMD they serialise).  Each wave reduces its own partial sum
+// after every product (reduction is a ring map, so the halves add up to the
+// residual modulo p); the halves meet in LDS before and after the inverse
+// step.
+//
+// Operand layout: at MFMA step s lane l supplies A(l % 16, k) and
+// B(k, l % 16) with k = 16 (l / 16) + 8h + s, s < 8, so each lane reads 8
+// consecutive entries of its row of T' (two 16-byte loads straight from
+// global memory) and the X blocks in LDS are read along k; the result
+// D(i, j) sits in lane j + 16 (i % 4), register i / 4.  LDS blocks are
+// 64 x 16 doubles with a spare row after every 16 so that the k-rows read
+// together (k and k + 16) fall in opposite halves of the banks.
+constexpr int LT = 512;                // threads per leaf workgroup
+constexpr int LW = 16;                 // columns per workgroup
+constexpr int KROWS = 68;              // 64 rows + one spare per 16
+constexpr int OPB = KROWS * LW;        // doubles per LDS operand block
+constexpr int NSB = TRSM_LEAF_MAX / 64;
+
+__device__ __forceinline__ int krow(int k) { return k + (k >> 4); }
+
+__device__ __forceinline__ void load_row8(const uint32_t *src, uint4 (&v)[2])
+{
+    const uint4 *s = (const uint4 *)src;
+    v[0] = s[0];
+    v[1] = s[1];
+}
+
+__device__ __forceinline__ uint32_t word(const uint4 (&v)[2], int s)
+{
+    const uint4 &q = v[s >> 2];
+    switch (s & 3) {
+    case 0: return q.x;
+    case 1: return q.y;
+    case 2: return q.z;
+    default: return q.w;
     }
 }
 
-int grid_for(int64_t total)
+// This lane's 8 B-operand entries of the LDS block `xb` (k = k0 + s).
+__device__ __forceinline__ void read_x(const double *xb, int k0, int col, double (&xv)[8])
 {
-    int64_t g = (total + TT - 1) / TT;
-    if (g > 65536) g = 65536;
-    return g < 1 ? 1 : (int)g;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) xv[s] = xb[krow(k0 + s) * LW + col];
 }
+
+// acc (+)= sign * A X over this wave's half of a 64-deep product: A's row
+// for this lane in `row` (8 residues), X's entries in `xv`.
+template <bool SPLIT>
+__device__ __forceinline__ void product(const uint4 (&row)[2], const double (&xv)[8],
+                                        double sign, uint32_t p, uint32_t half, v4d &acc,
+                                        v4d &acc_hi)
+{
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const double t = sign * (double)center(word(row, s), p, half);
+        const double x = xv[s];
+        if (SPLIT) {
+            const double th = __builtin_rint(t * (1.0 / 32768.0));
+            const double tl = __builtin_fma(-th, 32768.0, t);
+            acc_hi = __builtin_amdgcn_mfma_f64_16x16x4f64(th, x, acc_hi, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(tl, x, acc, 0, 0, 0);
+        } else {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(t, x, acc, 0, 0, 0);
+        }
+    }
+}
+
+template <bool SPLIT>
+__device__ __forceinline__ void settle(v4d &acc, v4d &acc_hi, double pd, double pinv)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double v = acc[r];
+        if (SPLIT) v = __builtin_fma(reduce_c(acc_hi[r], pd, pinv), 32768.0, v);
+        acc[r] = reduce_c(v, pd, pinv);
+    }
+}
+
+// NS = number of 64-row sub-blocks in the leaf; the whole walk unrolls.
+// Global loads take microseconds, so each row's operands are requested a row
+// ahead: when row t starts, the entries of B, the inverse block and the
+// first T' block of row t + 1 are requested (double-buffered by parity); its
+// remaining T' blocks follow once row t's products have freed their
+// registers.  The X entries of the next product are read from LDS before the
+// current product's matrix-core steps (scheduling barriers keep the
+// compiler from sinking the reads).
+template <bool SPLIT, int NS>
+__global__ __launch_bounds__(LT) void k_trsm_leaf(const uint32_t *Tn, int64_t ldn,
+                                                  const uint32_t *Tinv, int lower, int64_t r0,
+                                                  uint32_t *B, int64_t ldb, int64_t m, int64_t n,
+                                                  uint32_t p, double pinv)
+{
+    __shared__ __attribute__((aligned(16))) double sC[2][OPB]; // residual halves
+    __shared__ __attribute__((aligned(16))) double sP[2][OPB]; // halves of X_b
+    __shared__ __attribute__((aligned(16))) double sX[NS * OPB];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = w & 3, h = w >> 2;
+    const int col = lane & 15, kg = lane >> 4;
+    const int k0 = 16 * kg + 8 * h; // this lane's first k of a product
+    const int64_t gcol = (int64_t)blockIdx.x * LW + col;
+    const bool colok = gcol < n;
+    const uint32_t half = (p - 1) / 2;
+    const double pd = (double)p;
+    // this lane's row of a 64 x 64 block: 16g + col, entries k0 .. k0 + 7
+    const int arow = 16 * g + col;
+
+    uint4 s0[2][2];                   // first T' block of a row (by parity)
+    uint4 sl[NS > 2 ? NS - 1 : 2][2]; // T' blocks 1.. of the current row
+    uint4 si[2][2];                   // inverse block of a row (by parity)
+    uint32_t braw[2][4];              // a row's entries of B (by parity; h = 0)
+    auto sub = [&](int t) { return lower ? t : NS - 1 - t; };
+    auto trow = [&](int t) { return Tn + (r0 + 64 * sub(t) + arow) * ldn + r0 + k0; };
+    auto early = [&](int t) {
+        const int64_t rb = r0 + 64 * sub(t);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gr = rb + 16 * g + kg + 4 * r;
+            braw[t & 1][r] = h == 0 && gr < m && colok ? B[gr * ldb + gcol] : 0u;
+        }
+        load_row8(Tinv + (int64_t)4096 * (rb >> 6) + arow * 64 + k0, si[t & 1]);
+        if (t > 0) load_row8(trow(t) + 64 * sub(0), s0[t & 1]);
+    };
+    auto late = [&](int t) {
+#pragma unroll
+        for (int u = 1; u < t; ++u) load_row8(trow(t) + 64 * sub(u), sl[u]);
+    };
+    early(0);
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int b = sub(t);
+        const int64_t rb = r0 + 64 * b;
+        if (t + 1 < NS) early(t + 1);
+        v4d acc, acc_hi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = (double)center(braw[t & 1][r], p, half);
+        double xv[2][8];
+        if (t > 0) read_x(sX + sub(0) * OPB, k0, col, xv[0]);
+#pragma unroll
+        for (int u = 0; u < t; ++u) {
+            if (u + 1 < t) read_x(sX + sub(u + 1) * OPB, k0, col, xv[(u + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (SPLIT) acc_hi = v4d{0.0, 0.0, 0.0, 0.0};
+            product<SPLIT>(u == 0 ? s0[t & 1] : sl[u], xv[u & 1], -1.0, p, half, acc, acc_hi);
+            settle<SPLIT>(acc, acc_hi, pd, pinv);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (t + 1 < NS) late(t + 1);
+        // X_b = inv(T'_bb) R_b with R_b = the two halves' sum, read along k
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sC[h][krow(16 * g + kg + 4 * r) * LW + col] = acc[r];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int e = krow(k0 + s) * LW + col;
+            xv[0][s] = reduce_c(sC[0][e] + sC[1][e], pd, pinv);
+        }
+        v4d x = {0.0, 0.0, 0.0, 0.0}, x_hi = {0.0, 0.0, 0.0, 0.0};
+        product<SPLIT>(si[t & 1], xv[0], 1.0, p, half, x, x_hi);
+        settle<SPLIT>(x, x_hi, pd, pinv);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sP[h][krow(16 * g + kg + 4 * r) * LW + col] = x[r];
+        __syncthreads();
+        // wave (g, h) finishes rows kg + 4r, r in {2h, 2h + 1}, of its block
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int i = 16 * g + kg + 4 * (2 * h + rr);
+            const int e = krow(i) * LW + col;
+            const double v = reduce_c(sP[0][e] + sP[1][e], pd, pinv);
+            sX[b * OPB + e] = v;
+            const int64_t gr = rb + i;
+            if (gr < m && colok) B[gr * ldb + gcol] = canon_f64(v, pd, pinv, p);
+        }
+        __syncthreads();
+    }
+}
+
+template <bool SPLIT, int NS>
+void launch_leaf_ns(dim3 grid, hipStream_t st, const uint32_t *Tn, int64_t ldn,
+                    const uint32_t *Tinv, int lower, int64_t r0, uint32_t *B, int64_t ldb,
+                    int64_t m, int64_t n, uint32_t p)
+{
+    hipLaunchKernelGGL((k_trsm_leaf<SPLIT, NS>), grid, dim3(LT), 0, st, Tn, ldn, Tinv, lower, r0,
+                       B, ldb, m, n, p, 1.0 / (double)p);
+}
+
+template <bool SPLIT>
+void launch_leaf(int ns, dim3 grid, hipStream_t st, const uint32_t *Tn, int64_t ldn,
+                 const uint32_t *Tinv, int lower, int64_t r0, uint32_t *B, int64_t ldb,
+                 int64_t m, int64_t n, uint32_t p)
+{
+    static_assert(NSB == 8, "one instantiation per sub-block count");
+    switch (ns) {
+#define FF_LEAF_CASE(k)                                                                        \
+    case k: launch_leaf_ns<SPLIT, k>(grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, m, n, p); break;
+        FF_LEAF_CASE(1) FF_LEAF_CASE(2) FF_LEAF_CASE(3) FF_LEAF_CASE(4)
+        FF_LEAF_CASE(5) FF_LEAF_CASE(6) FF_LEAF_CASE(7) FF_LEAF_CASE(8)
+#undef FF_LEAF_CASE
+    default: break;
+    }
+}
+
 
 } // namespace
 
@@ -170,32 +429,47 @@ hipError_t launch_trsm_dinv(const uint32_t *T, int64_t ldt, int64_t m, uint32_t 
 }
 
 hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower, int64_t m,
-                            uint32_t p, const uint32_t *dinv, uint32_t *Tn, hipStream_t st)
+                            int64_t ldn, uint32_t p, const uint32_t *dinv, uint32_t *Tn,
+                            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_trsm_prep, dim3(grid_for(m * m)), dim3(TT), 0, st, T, ldt, trans, lower,
-                       m, p, 1.0 / (double)p, dinv, Tn);
+    const int64_t tiles = (ldn / 64) * (ldn / 64);
+    if (tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_trsm_prep, dim3((unsigned)tiles), dim3(TT), 0, st, T, ldt, trans, lower,
+                       m, ldn, p, 1.0 / (double)p, dinv, Tn);
     return hipGetLastError();
 }
 
 hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uint32_t p,
                              uint32_t alpha, const uint32_t *dinv, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_trsm_scale, dim3(grid_for(m * n)), dim3(TT), 0, st, B, ldb, m, n, p,
-                       1.0 / (double)p, alpha, dinv);
+    const dim3 grid((unsigned)((n + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(m, 4096));
+    hipLaunchKernelGGL(k_trsm_scale, grid, dim3(TT), 0, st, B, ldb, m, n, p, 1.0 / (double)p,
+                       alpha, dinv);
     return hipGetLastError();
 }
 
-hipError_t launch_trsm_diag(const uint32_t *Tn, int64_t m, int lower, int64_t r0, int bs,
-                            uint32_t *B, int64_t ldb, int64_t n, uint32_t p, int exact,
-                            hipStream_t st)
+hipError_t launch_trsm_inv(const uint32_t *Tn, int64_t ldn, int lower, uint32_t p, int split,
+                           uint32_t *Tinv, hipStream_t st)
 {
-    const dim3 grid((unsigned)((n + TT - 1) / TT));
-    if (exact)
-        hipLaunchKernelGGL(k_trsm_diag<true>, grid, dim3(TT), 0, st, Tn, m, lower, r0, bs, B, ldb,
-                           n, p, 1.0 / (double)p);
+    const dim3 grid((unsigned)(ldn / 64 * 4));
+    if (split)
+        hipLaunchKernelGGL(k_trsm_inv<true>, grid, dim3(TT), 0, st, Tn, ldn, lower, p,
+                           1.0 / (double)p, Tinv);
     else
-        hipLaunchKernelGGL(k_trsm_diag<false>, grid, dim3(TT), 0, st, Tn, m, lower, r0, bs, B,
-                           ldb, n, p, 1.0 / (double)p);
+        hipLaunchKernelGGL(k_trsm_inv<false>, grid, dim3(TT), 0, st, Tn, ldn, lower, p,
+                           1.0 / (double)p, Tinv);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_leaf(const uint32_t *Tn, int64_t ldn, const uint32_t *Tinv, int lower,
+                            int64_t r0, int rows, uint32_t *B, int64_t ldb, int64_t m, int64_t n,
+                            uint32_t p, int split, hipStream_t st)
+{
+    const int ns = (rows + 63) / 64;
+    if (rows < 1 || ns > NSB || r0 % 64) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + LW - 1) / LW));
+    if (split) launch_leaf<true>(ns, grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, m, n, p);
+    else launch_leaf<false>(ns, grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, m, n, p);
     return hipGetLastError();
 }
 

@@ -4,18 +4,22 @@
 // Normalisation (Section 4.2): with D the diagonal of op(T), T' = D^-1 op(T)
 // has a unit diagonal and T' X = alpha D^-1 B involves ring operations only.
 // The solve is the block recursive algorithm of Section 4.1: split the rows
-// in two, solve the part the triangle allows first, subtract its
-// contribution from the other part with one fgemm (C <- C - A X, reduced in
-// the GEMM epilogue), solve the other part.  The recursion stops at
-// diagonal blocks of TRSM_BS rows, solved one column per thread with
-// products summed exactly in binary64 and one reduction per unknown.
+// in two at a multiple of 64, solve the part the triangle allows first,
+// subtract its contribution from the other part with one fgemm
+// (C <- C - A X, reduced in the GEMM epilogue), solve the other part.  The
+// recursion stops at leaves of at most `leaf` rows (512 unless FF_TRSM_LEAF
+// says otherwise), each solved by one kernel launch: the inverses of all
+// 64 x 64 diagonal blocks are formed once up front, and the leaf kernel
+// walks its 64-row sub-blocks on the FP64 matrix cores (residual, then
+// inverse times residual).
 //
 // The paper's cascades (blocks of t_del rows solved over Z by a numerical
 // trsm, updates left unreduced below t_update) save reduction passes around
 // CPU BLAS calls; here the reduction of an update is fused into the fgemm
-// epilogue and the diagonal kernel reduces each unknown once, so the
+// epilogue and the leaf reduces after every 64-deep product, so the
 // recursion reduces at every level at no extra pass.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "ff_profile.h"
@@ -25,14 +29,28 @@ namespace ff {
 
 namespace {
 
+// Leaf size: FF_TRSM_LEAF (a multiple of 64 up to TRSM_LEAF_MAX) or 512.
+int64_t trsm_leaf_rows()
+{
+    const char *e = std::getenv("FF_TRSM_LEAF");
+    if (e && *e) {
+        const int v = std::atoi(e);
+        if (v >= 64 && v <= TRSM_LEAF_MAX && v % 64 == 0) return v;
+    }
+    return 512;
+}
+
 struct Trsm {
     uint32_t p;
     int lower; // op(T) lower triangular
     int64_t m, n;
-    const uint32_t *Tn;
+    const uint32_t *Tn; // ldn x ldn
+    int64_t ldn;
+    const uint32_t *Tinv; // ldn / 64 blocks of 64 x 64
     uint32_t *B;
     int64_t ldb;
-    int exact;
+    int64_t leaf;
+    int split;
     ff_opts o; // inner fgemm options (stream set, no validation)
     hipStream_t st;
 };
@@ -40,29 +58,29 @@ struct Trsm {
 int solve(const Trsm &c, int64_t r0, int64_t r1)
 {
     const int64_t size = r1 - r0;
-    if (size <= TRSM_BS) {
+    if (size <= c.leaf) {
         FF_HIP_CHECK(FF_TIMED(PROF_SLICE, c.st,
-                              launch_trsm_diag(c.Tn, c.m, c.lower, r0, (int)size, c.B, c.ldb,
-                                               c.n, c.p, c.exact, c.st)));
+                              launch_trsm_leaf(c.Tn, c.ldn, c.Tinv, c.lower, r0, (int)size, c.B,
+                                               c.ldb, c.m, c.n, c.p, c.split, c.st)));
         return FF_OK;
     }
-    // split at a multiple of the block size near the middle
-    const int64_t mid = r0 + round_up(size / 2, TRSM_BS);
+    // split at a multiple of 64 near the middle
+    const int64_t mid = r0 + round_up(size / 2, 64);
     const uint32_t minus1 = c.p - 1;
     int rc;
     if (!c.lower) {
         // upper: rows [mid, r1) first, then B[r0:mid] -= T'[r0:mid, mid:r1] X[mid:r1]
         if ((rc = solve(c, mid, r1))) return rc;
         if ((rc = ff_fgemm_ex(c.p, 0, 0, mid - r0, c.n, r1 - mid, minus1,
-                              c.Tn + r0 * c.m + mid, c.m, c.B + mid * c.ldb, c.ldb, 1,
+                              c.Tn + r0 * c.ldn + mid, c.ldn, c.B + mid * c.ldb, c.ldb, 1,
                               c.B + r0 * c.ldb, c.ldb, &c.o)))
             return rc;
         return solve(c, r0, mid);
     }
     // lower: rows [r0, mid) first, then B[mid:r1] -= T'[mid:r1, r0:mid] X[r0:mid]
     if ((rc = solve(c, r0, mid))) return rc;
-    if ((rc = ff_fgemm_ex(c.p, 0, 0, r1 - mid, c.n, mid - r0, minus1, c.Tn + mid * c.m + r0,
-                          c.m, c.B + r0 * c.ldb, c.ldb, 1, c.B + mid * c.ldb, c.ldb, &c.o)))
+    if ((rc = ff_fgemm_ex(c.p, 0, 0, r1 - mid, c.n, mid - r0, minus1, c.Tn + mid * c.ldn + r0,
+                          c.ldn, c.B + r0 * c.ldb, c.ldb, 1, c.B + mid * c.ldb, c.ldb, &c.o)))
         return rc;
     return solve(c, mid, r1);
 }
@@ -111,13 +129,17 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
         FF_HIP_CHECK(launch_scale(B, ldb, m, n, p, 0, st));
         return FF_OK;
     }
-    // workspace slot 1 (the inner fgemm calls use slot 0): T', dinv, a flag
-    const int64_t tn_bytes = round_up(m * m * 4, 256), di_bytes = round_up(m * 4, 256);
+    // workspace slot 1 (the inner fgemm calls use slot 0): T', the inverses
+    // of its diagonal blocks, dinv, a flag
+    const int64_t ldn = round_up(m, 64);
+    const int64_t tn_bytes = ldn * ldn * 4, ti_bytes = ldn * 64 * 4,
+                  di_bytes = round_up(m * 4, 256);
     void *wsv = nullptr;
-    if ((rc = workspace(st, (size_t)(tn_bytes + di_bytes + 256), &wsv, 1))) return rc;
+    if ((rc = workspace(st, (size_t)(tn_bytes + ti_bytes + di_bytes + 256), &wsv, 1))) return rc;
     uint32_t *Tn = (uint32_t *)wsv;
-    uint32_t *dinv = (uint32_t *)((char *)wsv + tn_bytes);
-    unsigned *bad = (unsigned *)((char *)wsv + tn_bytes + di_bytes);
+    uint32_t *Tinv = (uint32_t *)((char *)wsv + tn_bytes);
+    uint32_t *dinv = (uint32_t *)((char *)wsv + tn_bytes + ti_bytes);
+    unsigned *bad = (unsigned *)((char *)wsv + tn_bytes + ti_bytes + di_bytes);
     const int lower = (uplo == FF_LOWER) ^ (transT == FF_TRANS);
     FF_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), st));
     FF_HIP_CHECK(launch_trsm_dinv(T, ldt, m, p, diag == FF_UNIT, dinv, bad, st));
@@ -129,7 +151,7 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
             return fail(FF_EINVAL,
                         std::to_string(h) + " diagonal entries of T have no inverse modulo p");
     }
-    FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, p, dinv, Tn, st));
+    FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, ldn, p, dinv, Tn, st));
     if (alpha != 1 || diag != FF_UNIT) FF_HIP_CHECK(launch_trsm_scale(B, ldb, m, n, p, alpha, dinv, st));
     Trsm c;
     c.p = p;
@@ -137,10 +159,16 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
     c.m = m;
     c.n = n;
     c.Tn = Tn;
+    c.ldn = ldn;
+    c.Tinv = Tinv;
     c.B = B;
     c.ldb = ldb;
-    const double h = (double)(p / 2);
-    c.exact = (double)TRSM_BS * h * h + h <= 9007199254740992.0;
+    c.leaf = trsm_leaf_rows();
+    // 64-term sums of centered products (|t| <= p/2, |x| <= p/2 + 2) plus a
+    // residual stay exact integers in binary64 up to 2^53
+    const double h = (double)(p / 2), hx = h + 2.0;
+    c.split = !(64.0 * h * hx + hx <= 9007199254740992.0);
+    FF_HIP_CHECK(launch_trsm_inv(Tn, ldn, lower, p, c.split, Tinv, st));
     c.o = o;
     c.o.stream = (void *)st;
     c.o.validate = 0;

@@ -111,3 +111,17 @@ def test_trsm_full_size_sampled(lower):
     lhs = oracle.fgemm_entries(p, Te, X, rows, cols)
     rhs = (alpha * B[rows, cols].astype(np.int64) % p).astype(np.uint32)
     assert np.array_equal(lhs, rhs)
+
+
+@pytest.mark.parametrize("leaf", ["64", "192", "512"])
+@pytest.mark.parametrize("p", [8388593, 2147483647], ids=["binary64", "split"])
+def test_trsm_leaf_sizes(monkeypatch, p, leaf):
+    # FF_TRSM_LEAF sets the rows per leaf launch (1 to 8 sub-blocks of 64);
+    # m = 1100 leaves a ragged last sub-block in every leaf size
+    monkeypatch.setenv("FF_TRSM_LEAF", leaf)
+    m, n = 1100, 70
+    for lower in (0, 1):
+        T = tri(p, m, 101 + lower)
+        B = synth.residues(synth.seed_for(102, 2), (m, n), p)
+        got = solve_gpu(p, T, B, 7, lower, 1, 0)
+        assert np.array_equal(got, oracle.ftrsm(p, T, B, 7, lower, trans=True)), lower
