@@ -12,6 +12,9 @@ Contents
   reduction after every multiply-add).
 * ``ftrsm``: the triangular solve op(T) X = alpha B mod p of Section 4 by
   plain substitution, every multiply-add reduced.
+* ``lqup`` / ``lqup_factors`` / ``det``: the LQUP factorisation of Section
+  5.1 by plain row-by-row elimination (first nonzero column as pivot), its
+  explicit factors, and the determinant read off U (Section 6).
 * ``oracle.bounds``: the paper's accumulation and growth bounds (eq. (1),
   eq. (2), Theorem 3.1, Corollaries 3.2-3.4) in exact Python integers.
 * ``oracle.winograd``: Winograd's variant in exact Python integers (the
@@ -66,6 +69,9 @@ def _load(plant=None):
     lib.oracle_ftrsm.argtypes = [_U32, _INT, _INT, _INT, _I64, _I64, _U32, ctypes.c_void_p,
                                  _I64, ctypes.c_void_p, _I64]
     lib.oracle_ftrsm.restype = _INT
+    lib.oracle_lqup.argtypes = [_U32, _I64, _I64, ctypes.c_void_p, _I64, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_lqup.restype = _INT
     _libs[key] = lib
     return lib
 
@@ -209,3 +215,74 @@ def ftrsm(p, T, B, alpha=1, lower=False, trans=False, unit=False, plant=None):
     if rc != 0:
         raise ValueError("oracle_ftrsm rejected its arguments")
     return X
+
+
+def lqup(p, A, plant=None):
+    """LQUP of A over Z/p (Section 5.1) in the compressed in-place form
+    written out in oracle.c.  Returns (F, rank, pivrows, colperm): F the
+    factored matrix (a new array), pivrows the pivot rows in order followed
+    by the dependent rows, colperm[j] the input column at position j.
+    Raises ZeroDivisionError when a nonzero pivot has no inverse modulo p."""
+    F = np.array(A, dtype=np.uint32, order="C", copy=True)
+    m, n = F.shape
+    rank = np.zeros(1, dtype=np.int64)
+    piv = np.zeros(max(m, 1), dtype=np.int64)
+    perm = np.zeros(max(n, 1), dtype=np.int64)
+    rc = _load(plant).oracle_lqup(p, m, n, _ptr(F), max(n, 1), rank.ctypes.data,
+                                  piv.ctypes.data, perm.ctypes.data)
+    if rc == -2:
+        raise ZeroDivisionError("a nonzero pivot has no inverse modulo p")
+    if rc != 0:
+        raise ValueError("oracle_lqup rejected its arguments")
+    return F, int(rank[0]), piv[:m].copy(), perm[:n].copy()
+
+
+def lqup_factors(p, F, rank, pivrows):
+    """Explicit factors from the compressed form: L (m x m unit lower
+    triangular, original row order) and QU (m x n: U's row k at row
+    pivrows[k], zero rows elsewhere), with A[:, colperm] = L QU mod p."""
+    m, n = F.shape
+    L = np.eye(m, dtype=np.uint32)
+    QU = np.zeros((m, n), dtype=np.uint32)
+    rank_above = 0
+    is_piv = np.zeros(m, dtype=bool)
+    is_piv[pivrows[:rank]] = True
+    for i in range(m):
+        for j in range(rank_above):
+            L[i, pivrows[j]] = F[i, j]
+        if is_piv[i]:
+            QU[i, rank_above:] = F[i, rank_above:]
+            rank_above += 1
+    return L, QU
+
+
+def permutation_sign(perm):
+    """+1 or -1: the parity of a permutation given as an index array."""
+    perm = list(perm)
+    seen = [False] * len(perm)
+    sign = 1
+    for i in range(len(perm)):
+        if seen[i]:
+            continue
+        j, length = i, 0
+        while not seen[j]:
+            seen[j] = True
+            j = perm[j]
+            length += 1
+        if length % 2 == 0:
+            sign = -sign
+    return sign
+
+
+def det(p, A, plant=None):
+    """Determinant of a square A over Z/p (Section 6): 0 below full rank,
+    else the product of U's diagonal times the sign of the column
+    permutation (every row is then a pivot row, in order)."""
+    F, r, piv, perm = lqup(p, A, plant)
+    n = F.shape[0]
+    if r < n:
+        return 0
+    d = 1
+    for k in range(n):
+        d = d * int(F[k, k]) % p
+    return d if permutation_sign(perm) > 0 else (p - d) % p

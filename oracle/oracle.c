@@ -298,3 +298,72 @@ int oracle_ftrsm(uint32_t p, int uplo, int trans, int diag, int64_t m, int64_t n
     }
     return 0;
 }
+
+/* LQUP factorisation (Section 5.1, the triangularisation of Ibarra, Moran
+ * and Hui): A = L Q U P with L m x m unit lower triangular, Q and P
+ * permutations and U m x n upper triangular whose first r = rank(A) rows are
+ * nonzero.  Section 6 reads the rank off U (its nonzero rows) and the
+ * determinant as the product of U's diagonal.
+ *
+ * Pivots are taken row by row, in order.  Row i, already reduced by every
+ * pivot found above it, pivots on its first nonzero entry among the columns
+ * not used by a pivot yet; that column is brought to position k (the index
+ * of the new pivot) by exchanging two whole columns.  The rows below are then
+ * reduced: row i2 gets the multiplier f = A[i2][k] / A[i][k], stored at
+ * A[i2][k], and loses f times row i on the columns after k.  A row with no
+ * nonzero entry left is dependent: it takes no pivot.
+ *
+ * Storage (compressed, in place, as the paper's implementation keeps L): row
+ * i keeps its position; with k_i pivots found above it, A[i][j] for j < k_i
+ * is row i's multiplier on pivot j, and A[i][j] for j >= k_i holds U's row
+ * (pivot rows, the pivot itself at j = k_i) or 0 (dependent rows), columns in
+ * the permuted order.  pivrows[0..r) lists the pivot rows in order and
+ * pivrows[r..m) the dependent rows in increasing order; colperm[j] is the
+ * input column now at position j.  With both, A[:, colperm] = L * (QU) where
+ * (QU)[pivrows[k]] = U's row k.
+ *
+ * Returns 0; -1 on a bad argument; -2 when a nonzero pivot has no inverse
+ * modulo p (p not prime).
+ */
+int oracle_lqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t *rank,
+                int64_t *pivrows, int64_t *colperm)
+{
+    if (p < 2 || m < 0 || n < 0 || (m > 0 && n > 0 && lda < n)) return -1;
+    const u128 P = p;
+    for (int64_t j = 0; j < n; ++j) colperm[j] = j;
+    int64_t k = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        uint32_t *ri = A + i * lda;
+        int64_t c = -1;
+        for (int64_t j = k; j < n; ++j)
+            if (ri[j]) { c = j; break; }
+        if (c < 0) continue; /* dependent row */
+        if (c != k) {
+            for (int64_t r = 0; r < m; ++r) {
+                uint32_t *row = A + r * lda;
+                const uint32_t t = row[k]; row[k] = row[c]; row[c] = t;
+            }
+            const int64_t t = colperm[k]; colperm[k] = colperm[c]; colperm[c] = t;
+        }
+        const int64_t inv = inv_euclid(ri[k], p);
+        if (inv < 0) return -2;
+        for (int64_t i2 = i + 1; i2 < m; ++i2) {
+            uint32_t *r2 = A + i2 * lda;
+            const u128 f = ((u128)r2[k] * (u128)inv) % P;
+            r2[k] = (uint32_t)f;
+            if (f == 0) continue;
+            /* planted: the column right after the pivot is not reduced */
+            for (int64_t j = PLANT(7) ? k + 2 : k + 1; j < n; ++j)
+                r2[j] = (uint32_t)((r2[j] + (P - f) * ri[j]) % P);
+        }
+        pivrows[k++] = i;
+    }
+    *rank = k;
+    /* dependent rows, in increasing order, after the pivot rows */
+    int64_t d = k;
+    for (int64_t i = 0, q = 0; i < m; ++i) {
+        if (q < k && pivrows[q] == i) { ++q; continue; }
+        pivrows[d++] = i;
+    }
+    return 0;
+}

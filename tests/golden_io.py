@@ -58,3 +58,28 @@ def trsm_params():
                 continue
             rows.append(tuple(int(x) for x in line.split()))
     return rows
+
+
+def lqup_hand():
+    cases = []
+    cur = None
+    with open(os.path.join(GOLDEN, "lqup_hand.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("case"):
+                cur = {}
+                for kv in line.split()[1:]:
+                    key, val = kv.split("=")
+                    cur[key] = int(val)
+                cases.append(cur)
+                continue
+            tag, rest = line.split(None, 1)
+            if tag in ("A", "F"):
+                cur[tag] = _mat(rest)
+            elif tag in ("pivrows", "colperm"):
+                cur[tag] = [int(x) for x in rest.split()]
+            else:
+                cur[tag] = int(rest)
+    return cases
