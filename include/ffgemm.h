@@ -174,6 +174,42 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
                 uint32_t alpha, const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb,
                 const ff_opts *opts);
 
+/* LQUP factorisation (Section 5.1): A = L Q U P over Z/pZ, p prime, with
+ * L m x m unit lower triangular, Q and P permutations and U m x n upper
+ * triangular whose first r = rank(A) rows are nonzero.
+ *
+ * A (device, m x n row-major, lda >= n, entries residues < p) is overwritten
+ * by the compressed form: row i keeps its position; with k_i pivots in the
+ * rows above it, A[i][j] for j < k_i is row i's multiplier on pivot j (L),
+ * and A[i][j] for j >= k_i is U's row (a pivot row, pivot at j = k_i) or 0
+ * (a dependent row), columns in the permuted order.  Pivots are chosen row
+ * by row, each row on its first nonzero entry among the columns no pivot
+ * uses yet (brought into place by exchanging two whole columns), so the
+ * result is unique.  On return (host arrays, caller-owned):
+ *   *rank       = r;
+ *   pivrows[m]  = the pivot rows in order, then the dependent rows in
+ *                 increasing order (Q: U's row k sits at row pivrows[k]);
+ *   colperm[n]  = colperm[j] is the input column now at position j (P), so
+ *                 that A_in[:, colperm] = L (QU).
+ * The call is synchronous (each block's pivots decide what follows).  The
+ * row recursion's solves and updates are ff_ftrsm and ff_fgemm calls that
+ * follow opts->path.  A nonzero pivot is assumed invertible (p prime);
+ * validate checks the entries of A first.  Workspace: about
+ * 4 min(m, n)(m + n) bytes per stream, besides those of fgemm and ftrsm. */
+int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t *rank,
+             int64_t *pivrows, int64_t *colperm, const ff_opts *opts);
+
+/* rank(A) over Z/pZ (Section 6: the nonzero rows of U).  A is overwritten
+ * by its LQUP factorisation as in ff_flqup. */
+int ff_frank(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t *rank,
+             const ff_opts *opts);
+
+/* det(A) over Z/pZ for square A (Section 6: the product of U's diagonal,
+ * with the sign of the column permutation; 0 below full rank), in *det.
+ * n = 0 gives 1.  A is overwritten by its LQUP factorisation. */
+int ff_fdet(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *det,
+            const ff_opts *opts);
+
 /* The plan ff_fgemm_ex would follow for these sizes (host-only). */
 int ff_plan_query(uint32_t p, int transA, int transB,
                   int64_t m, int64_t n, int64_t k,

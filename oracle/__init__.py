@@ -244,15 +244,16 @@ def lqup_factors(p, F, rank, pivrows):
     m, n = F.shape
     L = np.eye(m, dtype=np.uint32)
     QU = np.zeros((m, n), dtype=np.uint32)
-    rank_above = 0
     is_piv = np.zeros(m, dtype=bool)
     is_piv[pivrows[:rank]] = True
+    # pivots in the rows above row i
+    above = np.concatenate(([0], np.cumsum(is_piv)[:-1]))
+    prow = np.asarray(pivrows[:rank])
     for i in range(m):
-        for j in range(rank_above):
-            L[i, pivrows[j]] = F[i, j]
+        ka = int(above[i])
+        L[i, prow[:ka]] = F[i, :ka]
         if is_piv[i]:
-            QU[i, rank_above:] = F[i, rank_above:]
-            rank_above += 1
+            QU[i, ka:] = F[i, ka:]
     return L, QU
 
 

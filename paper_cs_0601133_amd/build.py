@@ -26,7 +26,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # Per-source flags.  The FP64 kernels fold their accumulators with vector
 # ALU code between matrix-core steps; with accumulators in AGPRs the
 # compiler would move all of them to VGPRs and back around every fold.
-PER_FILE = {"kernels_f64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+PER_FILE = {"kernels_f64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+            # the LQUP panel's walk over its 64 rows must unroll completely so
+            # that each thread's column stays in registers
+            "kernels_lqup.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 
 
 def sources():

@@ -232,6 +232,28 @@ hipError_t launch_trsm_leaf(const uint32_t *Tn, int64_t ldn, const uint32_t *Tin
                             int64_t r0, int rows, uint32_t *B, int64_t ldb, int64_t m, int64_t n,
                             uint32_t p, int split, hipStream_t st);
 
+// LQUP (kernels_lqup.hip): rows and window columns of one pivot panel.
+constexpr int LQUP_PANEL = 64;
+constexpr int LQUP_WINDOW = 128;
+// Factors rows [i0, i0 + nr) over columns [k, k + W) (every entry already
+// reduced by the pivots above); out as described in kernels_lqup.hip
+// (3 + 2 LQUP_PANEL int32).  whole: the window reaches the last column.
+hipError_t launch_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
+                             int whole, uint32_t p, int32_t *out, hipStream_t st);
+// Column exchanges pairs[2j] <-> pairs[2j + 1] in order, rows outside
+// [skip_lo, skip_hi).
+hipError_t launch_lqup_swap(uint32_t *A, int64_t lda, int64_t m, int64_t skip_lo, int64_t skip_hi,
+                            const int64_t *pairs, int npairs, hipStream_t st);
+// U[j][c] = A[rows[j]][c0 + c].
+hipError_t launch_lqup_gather(const uint32_t *A, int64_t lda, const int64_t *rows, int64_t r,
+                              int64_t c0, int64_t ncols, uint32_t *U, int64_t ldu, hipStream_t st);
+// dst = src^T (src rows x cols).
+hipError_t launch_lqup_transpose(const uint32_t *src, int64_t lds, int64_t rows, int64_t cols,
+                                 uint32_t *dst, int64_t ldd, hipStream_t st);
+// out[r] = first c in [c0, n) with A[i0 + r][c] != 0, or -1, for r < nr.
+hipError_t launch_lqup_first_nonzero(const uint32_t *A, int64_t lda, int64_t i0, int64_t nr,
+                                     int64_t c0, int64_t n, int64_t *out, hipStream_t st);
+
 // C <- (alpha * sum_s part[s] + beta*C) mod p over nsplit partial products
 // part[s][m][n] in [0, p).
 hipError_t launch_split_reduce(const uint32_t *part, int nsplit, int64_t m, int64_t n,

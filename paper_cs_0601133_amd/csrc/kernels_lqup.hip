@@ -1,0 +1,359 @@
+// Kernels of the LQUP factorisation over Z/pZ (Section 5.1).
+//
+// The factorisation is row recursive (lqup.cpp): blocks of up to 64 rows are
+// factored by one workgroup (k_lqup_panel), the rest of the work is the
+// triangular solve and the fgemm update of the recursion, plus the column
+// exchanges the pivots require (k_lqup_swap), the gathering of the pivot rows
+// (k_lqup_gather), transposes for the right-hand triangular solve
+// (k_lqup_transpose) and a search for pivots past the panel's window
+// (k_lqup_first_nonzero).
+#include "ff_device.h"
+#include "ff_internal.h"
+
+namespace ff {
+
+namespace {
+
+constexpr int PR = LQUP_PANEL;    // rows of a panel
+constexpr int PW = LQUP_WINDOW;   // columns of the panel's window
+constexpr int PT = 1024;          // threads: PW columns x PG row groups
+constexpr int PG = PT / PW;       // row groups
+constexpr int PQ = PR / PG;       // rows per group
+static_assert(PR == 64 && PW == 128, "panel: column tid % 128, rows 8 (tid / 128) + q");
+
+__device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
+{
+    return __builtin_fma(-__builtin_rint(x * pinv), pd, x);
+}
+
+// Inverse of a unit a modulo p (extended Euclid); 0 if a is not a unit.
+__device__ __forceinline__ uint32_t inv_mod(uint32_t a, uint32_t p)
+{
+    int64_t r0 = p, r1 = a % p, s0 = 0, s1 = 1;
+    while (r1 != 0) {
+        const int64_t q = r0 / r1, r2 = r0 - q * r1, s2 = s0 - q * s1;
+        r0 = r1; r1 = r2; s0 = s1; s1 = s2;
+    }
+    if (r0 != 1) return 0;
+    return (uint32_t)(s0 < 0 ? s0 + (int64_t)p : s0);
+}
+
+// One panel: rows [i0, i0 + nr) (nr <= 64) over the window of columns
+// [k, k + W) (W <= 128), every entry already reduced by the pivots above.
+// Thread (c, g) owns column c of the window and the contiguous rows
+// 8g .. 8g + 7; the walk over rows unrolls and a group whose rows are all
+// above the pivot row skips the update (the test is uniform per wave).
+// Rows are processed in order: a row pivots on its first nonzero entry at or
+// after column t (the next pivot index), exchanged into column t inside the
+// panel; a row with no such entry is dependent if the window reaches the
+// last column (whole), else the panel stops there (the caller searches the
+// columns past the window).  A window of 128 columns for 64 rows leaves
+// every row at least 64 candidate columns.
+//
+// Elimination is fraction free: below pivot row r (pivot value pi, entry a
+// of row r2 in column t) row r2 <- pi row r2 - a row r on the columns after
+// t, and a stays in column t.  Every row below a pivot is scaled by the same
+// factor S_t = pi_0 ... pi_{t-1} (products of the values found), so a / pi
+// is the exact multiplier and the true row is the stored one divided by
+// S_t; the inverses are taken once at the end, in parallel, instead of one
+// per pivot on the critical path.
+//
+// EXACT: entries as centered doubles, pi x - a y exact while
+// 2 (p/2 + 2)^2 <= 2^53; otherwise canonical residues and mulmod.
+//
+// out: [0] pivots t, [1] rows processed, [2] stuck, [3 + r] = pivot index
+// of processed row r or -1 (dependent), [3 + 64 + j] = window column that
+// pivot j came from (== j: no exchange).
+template <bool EXACT>
+__global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr,
+                                                   int64_t k, int W, int whole, uint32_t p,
+                                                   double pinv, int32_t *out)
+{
+    __shared__ double s_row[PW];       // pivot row, published
+    __shared__ double s_col[PR];       // column t, published
+    __shared__ double s_swap[2][PR];   // column exchange
+    __shared__ uint32_t s_piv[PR];     // pivot values (fraction-free, canonical)
+    __shared__ uint32_t s_inv[PR];     // their inverses
+    __shared__ uint32_t s_invS[PR + 1]; // inverse scale after j pivots
+    __shared__ int s_first[PW / 64];
+    __shared__ int s_rowpiv[PR];       // pivot index of a row, -1 dependent, -2 untouched
+    __shared__ int s_before[PR];       // pivots above the row when it was processed
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int c = tid % PW, g = tid / PW, r0g = PQ * g;
+    const uint32_t half = (p - 1) / 2;
+    const double pd = (double)p;
+
+    double v[PQ];
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+        const int r = r0g + q;
+        uint32_t u = 0;
+        if (r < nr && c < W) u = A[(i0 + r) * lda + k + c];
+        v[q] = EXACT ? (double)center(u, p, half) : (double)u;
+    }
+    if (tid < PR) {
+        s_rowpiv[tid] = -2;
+        s_before[tid] = 0;
+    }
+    __syncthreads();
+
+    int t = 0, nproc = 0, stuck = 0;
+    // every loop has a constant trip count (it unrolls; v[] stays in
+    // registers); rows past nr and rows after a stop are skipped by tests
+    // that are uniform across the workgroup
+#pragma unroll
+    for (int r = 0; r < PR; ++r) {
+        if (stuck || r >= nr) continue;
+        const int gr = r / PQ, qr = r % PQ;
+        // row r: publish it, and find its first nonzero at or after column t
+        if (g == gr) {
+            s_row[c] = v[qr];
+            const bool nz = c >= t && c < W && v[qr] != 0.0;
+            const uint64_t bal = __ballot(nz);
+            if (lane == 0) s_first[c / 64] = bal ? (c - lane) + __builtin_ctzll(bal) : PW;
+        }
+        __syncthreads();
+        int cmin = PW;
+#pragma unroll
+        for (int ww = 0; ww < PW / 64; ++ww) cmin = min(cmin, s_first[ww]);
+        if (cmin >= PW) {
+            if (!whole) {
+                stuck = 1;
+            } else {
+                if (tid == 0) { s_rowpiv[r] = -1; s_before[r] = t; }
+                ++nproc; // dependent row: zero from column t on
+            }
+            __syncthreads(); // s_first and s_row are rewritten by the next row
+            continue;
+        }
+        if (cmin != t) {
+            // exchange columns t and cmin in every row of the panel
+            if (c == t) {
+#pragma unroll
+                for (int q = 0; q < PQ; ++q) s_swap[0][r0g + q] = v[q];
+            }
+            if (c == cmin) {
+#pragma unroll
+                for (int q = 0; q < PQ; ++q) s_swap[1][r0g + q] = v[q];
+            }
+            __syncthreads();
+            if (c == t) {
+#pragma unroll
+                for (int q = 0; q < PQ; ++q) v[q] = s_swap[1][r0g + q];
+            }
+            if (c == cmin) {
+#pragma unroll
+                for (int q = 0; q < PQ; ++q) v[q] = s_swap[0][r0g + q];
+            }
+            if (g == gr && (c == t || c == cmin)) s_row[c] = v[qr];
+        }
+        // publish column t (the pivot and the entries below it)
+        if (c == t) {
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) s_col[r0g + q] = v[q];
+        }
+        if (tid == 0) {
+            s_rowpiv[r] = t;
+            s_before[r] = t;
+            out[3 + PR + t] = cmin;
+        }
+        __syncthreads();
+        const double pv = s_col[r];
+        if (tid == 0) {
+            const double pc = EXACT ? (pv < 0 ? pv + pd : pv) : pv;
+            s_piv[t] = (uint32_t)pc;
+        }
+        // rows below r, columns after t (groups entirely above r skip)
+        if (g >= gr && c > t && c < W) {
+            const double y = s_row[c];
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) {
+                const int r2 = r0g + q;
+                if (r2 > r && r2 < nr) {
+                    const double a = s_col[r2];
+                    if (EXACT) {
+                        v[q] = reduce_c(__builtin_fma(pv, v[q], -a * y), pd, pinv);
+                    } else {
+                        const uint32_t x1 = mulmod((uint32_t)pv, (uint32_t)v[q], p, pinv);
+                        const uint32_t x2 = mulmod((uint32_t)a, (uint32_t)y, p, pinv);
+                        v[q] = (double)(x1 >= x2 ? x1 - x2 : x1 + p - x2);
+                    }
+                }
+            }
+        }
+        ++t;
+        ++nproc;
+        __syncthreads(); // s_row, s_col and s_first are rewritten by the next row
+    }
+    // inverses of the pivots, and of the scales S_j = pi_0 ... pi_{j-1}
+    if (tid < t) s_inv[tid] = inv_mod(s_piv[tid], p);
+    __syncthreads();
+    if (tid < 64) {
+        // inclusive prefix product over lanes < t, then shifted by one
+        uint32_t x = lane < t ? s_inv[lane] : 1u;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x = mulmod(x, y, p, pinv);
+        }
+        s_invS[lane + 1] = x;
+        if (lane == 0) s_invS[0] = 1u;
+    }
+    __syncthreads();
+    // undo the scaling and store canonical residues
+    if (c < W) {
+        const uint32_t invc = c < t ? s_inv[c] : 0u;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int r = r0g + q;
+            if (r >= nr) continue;
+            const int rp = s_rowpiv[r];
+            const int before = rp == -2 ? t : s_before[r];
+            uint32_t u;
+            if (EXACT) {
+                const double x = v[q];
+                u = (uint32_t)(x < 0 ? x + pd : x);
+            } else {
+                u = (uint32_t)v[q];
+            }
+            if (c < before) u = mulmod(u, invc, p, pinv);         // multiplier a / pi
+            else u = mulmod(u, s_invS[before], p, pinv);          // row / S
+            A[(i0 + r) * lda + k + c] = u;
+        }
+    }
+    if (tid == 0) {
+        out[0] = t;
+        out[1] = nproc;
+        out[2] = stuck;
+    }
+    if (tid < PR) out[3 + tid] = s_rowpiv[tid];
+}
+
+// Column exchanges (c1, c2), in order, applied to every row outside
+// [skip_lo, skip_hi); one thread per row.
+__global__ __launch_bounds__(256) void k_lqup_swap(uint32_t *A, int64_t lda, int64_t m,
+                                                   int64_t skip_lo, int64_t skip_hi,
+                                                   const int64_t *pairs, int npairs)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= m || (r >= skip_lo && r < skip_hi)) return;
+    uint32_t *row = A + r * lda;
+    for (int j = 0; j < npairs; ++j) {
+        const int64_t c1 = pairs[2 * j], c2 = pairs[2 * j + 1];
+        const uint32_t x = row[c1];
+        row[c1] = row[c2];
+        row[c2] = x;
+    }
+}
+
+// U[j][c] = A[rows[j]][c0 + c] for j < r, c < ncols.
+__global__ __launch_bounds__(256) void k_lqup_gather(const uint32_t *A, int64_t lda,
+                                                     const int64_t *rows, int64_t r, int64_t c0,
+                                                     int64_t ncols, uint32_t *U, int64_t ldu)
+{
+    const int64_t j = blockIdx.y;
+    const uint32_t *src = A + rows[j] * lda + c0;
+    uint32_t *dst = U + j * ldu;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < ncols;
+         c += (int64_t)gridDim.x * 256)
+        dst[c] = src[c];
+}
+
+// dst[c][r] = src[r][c] for r < rows, c < cols, through 64 x 64 LDS tiles.
+__global__ __launch_bounds__(256) void k_lqup_transpose(const uint32_t *src, int64_t lds,
+                                                        int64_t rows, int64_t cols,
+                                                        uint32_t *dst, int64_t ldd)
+{
+    __shared__ uint32_t tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int rr = ty; rr < 64; rr += 4)
+        if (r0 + rr < rows && c0 + tx < cols) tile[rr][tx] = src[(r0 + rr) * lds + c0 + tx];
+    __syncthreads();
+    for (int cc = ty; cc < 64; cc += 4)
+        if (c0 + cc < cols && r0 + tx < rows) dst[(c0 + cc) * ldd + r0 + tx] = tile[tx][cc];
+}
+
+// out[r] = first column c in [c0, n) with A[i0 + r][c] != 0, or -1; one
+// workgroup per row.
+__global__ __launch_bounds__(256) void k_lqup_first_nonzero(const uint32_t *A, int64_t lda,
+                                                            int64_t i0, int64_t c0, int64_t n,
+                                                            int64_t *out)
+{
+    __shared__ int64_t s_min[4];
+    const int64_t r = blockIdx.x;
+    const uint32_t *row = A + (i0 + r) * lda;
+    int64_t best = INT64_MAX;
+    for (int64_t c = c0 + threadIdx.x; c < n; c += 256)
+        if (row[c] != 0) { best = c; break; }
+    // minimum over the workgroup
+    for (int d = 32; d > 0; d >>= 1) {
+        const int64_t o = __shfl_down(best, d, 64);
+        best = o < best ? o : best;
+    }
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t b = s_min[0];
+        for (int w = 1; w < 4; ++w) b = s_min[w] < b ? s_min[w] : b;
+        out[r] = b == INT64_MAX ? -1 : b;
+    }
+}
+
+} // namespace
+
+hipError_t launch_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
+                             int whole, uint32_t p, int32_t *out, hipStream_t st)
+{
+    if (nr < 1 || nr > PR || W < 1 || W > PW) return hipErrorInvalidValue;
+    const double h = (double)(p / 2) + 2.0;
+    const bool exact = 2.0 * h * h <= 9007199254740992.0;
+    if (exact)
+        hipLaunchKernelGGL(k_lqup_panel<true>, dim3(1), dim3(PT), 0, st, A, lda, i0, nr, k, W,
+                           whole, p, 1.0 / (double)p, out);
+    else
+        hipLaunchKernelGGL(k_lqup_panel<false>, dim3(1), dim3(PT), 0, st, A, lda, i0, nr, k, W,
+                           whole, p, 1.0 / (double)p, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lqup_swap(uint32_t *A, int64_t lda, int64_t m, int64_t skip_lo, int64_t skip_hi,
+                            const int64_t *pairs, int npairs, hipStream_t st)
+{
+    if (m <= 0 || npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lqup_swap, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, A, lda,
+                       m, skip_lo, skip_hi, pairs, npairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_lqup_gather(const uint32_t *A, int64_t lda, const int64_t *rows, int64_t r,
+                              int64_t c0, int64_t ncols, uint32_t *U, int64_t ldu, hipStream_t st)
+{
+    if (r <= 0 || ncols <= 0) return hipSuccess;
+    if (r > 65535) return hipErrorInvalidValue;
+    const unsigned gx = (unsigned)std::min<int64_t>((ncols + 255) / 256, 64);
+    hipLaunchKernelGGL(k_lqup_gather, dim3(gx, (unsigned)r), dim3(256), 0, st, A, lda, rows, r,
+                       c0, ncols, U, ldu);
+    return hipGetLastError();
+}
+
+hipError_t launch_lqup_transpose(const uint32_t *src, int64_t lds, int64_t rows, int64_t cols,
+                                 uint32_t *dst, int64_t ldd, hipStream_t st)
+{
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if ((rows + 63) / 64 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lqup_transpose, dim3((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64)),
+                       dim3(256), 0, st, src, lds, rows, cols, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_lqup_first_nonzero(const uint32_t *A, int64_t lda, int64_t i0, int64_t nr,
+                                     int64_t c0, int64_t n, int64_t *out, hipStream_t st)
+{
+    if (nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lqup_first_nonzero, dim3((unsigned)nr), dim3(256), 0, st, A, lda, i0, c0,
+                       n, out);
+    return hipGetLastError();
+}
+
+} // namespace ff

@@ -1,0 +1,307 @@
+// LQUP factorisation over Z/pZ (Section 5.1) and what Section 6 reads off
+// it: the rank and the determinant.
+//
+// A = L Q U P, computed in place in the compressed form: row i keeps its
+// position; with k_i pivots in the rows above it, its entries before column
+// k_i are its multipliers on those pivots and the rest is U's row (pivot
+// rows) or zero (dependent rows), columns in the permuted order.  Pivots are
+// chosen row by row, each row on its first nonzero entry among the columns no
+// pivot uses yet, exchanged into place; the factorisation is then unique.
+//
+// The algorithm is the row recursion the paper describes: factor the top
+// half (pivots T, Y = the rest of their U rows, in the pivot rows), then for
+// the bottom half [X Z] solve G T = X (the right-hand triangular solve, done
+// as T^T G^T = X^T with ftrsm on transposes), update Z <- Z - G Y with one
+// fgemm, and factor Z.  Blocks of 64 rows are factored by one workgroup
+// over a window of 128 columns (k_lqup_panel); the pivot rows' entries past
+// the window are then finished with a unit lower triangular ftrsm and the
+// panel's remaining rows with an fgemm.  When a row's window holds no pivot,
+// the remaining rows of the panel are searched over all columns from the
+// current rank on (k_lqup_first_nonzero): the first row with a nonzero is
+// the next pivot row (a column exchange brings its entry into place), the
+// rows before it are dependent.  Each panel's pivots
+// decide the sizes of what follows, so the host reads them back: the call is
+// synchronous.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "ff_runtime.h"
+
+namespace ff {
+
+namespace {
+
+struct Lqup {
+    uint32_t p;
+    int64_t m, n, lda;
+    uint32_t *A;
+    hipStream_t st;
+    ff_opts o;              // for the inner fgemm / ftrsm calls
+    int64_t k = 0;          // pivots so far
+    std::vector<int64_t> piv; // pivot rows in order
+    std::vector<char> dep;    // dependent rows
+    std::vector<int64_t> colperm;
+    // device scratch (workspace slot 2)
+    uint32_t *U = nullptr;  // gathered pivot rows
+    uint32_t *Xt = nullptr; // transposed X
+    int64_t *d_rows = nullptr, *d_pairs = nullptr, *d_first = nullptr;
+    int32_t *d_out = nullptr;
+};
+
+int fgemm_sub(const Lqup &c, int64_t m, int64_t n, int64_t k, const uint32_t *A, int64_t lda,
+              const uint32_t *B, int64_t ldb, uint32_t *C, int64_t ldc)
+{
+    // C <- C - A B
+    return ff_fgemm_ex(c.p, FF_NOTRANS, FF_NOTRANS, m, n, k, c.p - 1, A, lda, B, ldb, 1, C, ldc,
+                       &c.o);
+}
+
+// Column exchanges (pairs of absolute columns, in order) on the rows outside
+// [skip_lo, skip_hi), recorded in colperm.
+int exchange(Lqup &c, const std::vector<int64_t> &pairs, int64_t skip_lo, int64_t skip_hi)
+{
+    if (pairs.empty()) return FF_OK;
+    for (size_t j = 0; j < pairs.size(); j += 2) std::swap(c.colperm[pairs[j]], c.colperm[pairs[j + 1]]);
+    int rc = upload_async(c.st, pairs.data(), pairs.size() * sizeof(int64_t), c.d_pairs);
+    if (rc) return rc;
+    FF_HIP_CHECK(launch_lqup_swap(c.A, c.lda, c.m, skip_lo, skip_hi, c.d_pairs,
+                                  (int)(pairs.size() / 2), c.st));
+    return FF_OK;
+}
+
+// Rows [a, b), b - a <= LQUP_PANEL; the pivots found go to *found.
+int panel(Lqup &c, int64_t a, int64_t b, int64_t *found)
+{
+    const int64_t k_start = c.k;
+    int64_t i = a;
+    int32_t out[3 + 2 * LQUP_PANEL];
+    int64_t first[LQUP_PANEL];
+    while (i < b) {
+        if (c.k == c.n) { // no column left: the other rows are dependent
+            for (int64_t r = i; r < b; ++r) c.dep[r] = 1;
+            break;
+        }
+        const int W = (int)std::min<int64_t>(LQUP_WINDOW, c.n - c.k);
+        const int whole = c.k + W == c.n;
+        const int nr = (int)(b - i);
+        FF_HIP_CHECK(launch_lqup_panel(c.A, c.lda, i, nr, c.k, W, whole, c.p, c.d_out, c.st));
+        FF_HIP_CHECK(hipMemcpyAsync(out, c.d_out, sizeof(out), hipMemcpyDeviceToHost, c.st));
+        FF_HIP_CHECK(hipStreamSynchronize(c.st));
+        const int t = out[0], nproc = out[1], stuck = out[2];
+        std::vector<int64_t> pairs;
+        for (int j = 0; j < t; ++j) {
+            const int from = out[3 + LQUP_PANEL + j];
+            if (from != j) {
+                pairs.push_back(c.k + j);
+                pairs.push_back(c.k + from);
+            }
+        }
+        int rc = exchange(c, pairs, i, b); // the panel's own rows are done
+        if (rc) return rc;
+        for (int r = 0; r < nproc; ++r) {
+            if (out[3 + r] >= 0) c.piv.push_back(i + r);
+            else c.dep[i + r] = 1;
+        }
+        if (t > 0 && !whole) {
+            // the pivot rows [i, i + t) past the window: U = L_pp^-1 (row),
+            // L_pp the unit lower triangle of their multipliers
+            const int64_t nc = c.n - c.k - W;
+            uint32_t *T = c.A + i * c.lda + c.k;
+            rc = ff_ftrsm_ex(c.p, FF_LOWER, FF_NOTRANS, FF_UNIT, t, nc, 1, T, c.lda,
+                             c.A + i * c.lda + c.k + W, c.lda, &c.o);
+            if (rc) return rc;
+            if (nr - t > 0) {
+                rc = fgemm_sub(c, nr - t, nc, t, c.A + (i + t) * c.lda + c.k, c.lda,
+                               c.A + i * c.lda + c.k + W, c.lda,
+                               c.A + (i + t) * c.lda + c.k + W, c.lda);
+                if (rc) return rc;
+            }
+        }
+        c.k += t;
+        i += nproc;
+        if (!stuck) continue;
+        // rows [i, b) are fully reduced and row i is zero inside the window
+        // from column c.k on (the rows after it may not be): the first row
+        // with a nonzero entry from column c.k on is the next pivot row and
+        // the rows before it are dependent
+        FF_HIP_CHECK(launch_lqup_first_nonzero(c.A, c.lda, i, b - i, c.k, c.n, c.d_first, c.st));
+        FF_HIP_CHECK(hipMemcpyAsync(first, c.d_first, (b - i) * sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, c.st));
+        FF_HIP_CHECK(hipStreamSynchronize(c.st));
+        int64_t j = 0;
+        while (j < b - i && first[j] < 0) ++j;
+        for (int64_t r = 0; r < j; ++r) c.dep[i + r] = 1;
+        i += j;
+        if (i < b && first[j] != c.k) {
+            // bring row i's first nonzero into column c.k, in every row
+            rc = exchange(c, {c.k, first[j]}, 0, 0);
+            if (rc) return rc;
+        }
+    }
+    *found = c.k - k_start;
+    return FF_OK;
+}
+
+int rec(Lqup &c, int64_t a, int64_t b, int64_t *found)
+{
+    if (b - a <= LQUP_PANEL) return panel(c, a, b, found);
+    const int64_t mid = a + round_up((b - a) / 2, LQUP_PANEL);
+    const int64_t k0 = c.k;
+    int64_t r1 = 0, r2 = 0;
+    int rc = rec(c, a, mid, &r1);
+    if (rc) return rc;
+    const int64_t m2 = b - mid, nc = c.n - k0;
+    if (r1 > 0 && m2 > 0) {
+        // T (r1 x r1 upper) and Y: the U rows of the top half's pivots
+        rc = upload_async(c.st, c.piv.data() + k0, r1 * sizeof(int64_t), c.d_rows);
+        if (rc) return rc;
+        FF_HIP_CHECK(launch_lqup_gather(c.A, c.lda, c.d_rows, r1, k0, nc, c.U, nc, c.st));
+        // G T = X  <=>  T^T G^T = X^T
+        uint32_t *X = c.A + mid * c.lda + k0;
+        FF_HIP_CHECK(launch_lqup_transpose(X, c.lda, m2, r1, c.Xt, m2, c.st));
+        rc = ff_ftrsm_ex(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r1, m2, 1, c.U, nc, c.Xt, m2, &c.o);
+        if (rc) return rc;
+        FF_HIP_CHECK(launch_lqup_transpose(c.Xt, m2, r1, m2, X, c.lda, c.st));
+        if (nc > r1) {
+            rc = fgemm_sub(c, m2, nc - r1, r1, X, c.lda, c.U + r1, nc, X + r1, c.lda);
+            if (rc) return rc;
+        }
+    }
+    rc = rec(c, mid, b, &r2);
+    if (rc) return rc;
+    *found = r1 + r2;
+    return FF_OK;
+}
+
+} // namespace
+
+} // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t *rank,
+             int64_t *pivrows, int64_t *colperm, const ff_opts *opts)
+{
+    if (p < 2 || p > 0x7FFFFFFFu) return fail(FF_EINVAL, "p must be in [2, 2^31 - 1]");
+    if (m < 0 || n < 0) return fail(FF_EINVAL, "negative dimension");
+    if (!rank || (m > 0 && !pivrows) || (n > 0 && !colperm))
+        return fail(FF_EINVAL, "null output pointer");
+    if (m > 0 && n > 0 && (!A || lda < n)) return fail(FF_EINVAL, "A null or lda < n");
+    if (m > 0x7FFFFFFF || n > 0x7FFFFFFF) return fail(FF_EINVAL, "dimension too large");
+    for (int64_t j = 0; j < n; ++j) colperm[j] = j;
+    if (m == 0 || n == 0) {
+        *rank = 0;
+        for (int64_t i = 0; i < m; ++i) pivrows[i] = i;
+        return FF_OK;
+    }
+    ff_opts o = opts ? *opts : default_opts();
+    int rc = check_device();
+    if (rc) return rc;
+    Lqup c;
+    c.p = p;
+    c.m = m;
+    c.n = n;
+    c.lda = lda;
+    c.A = A;
+    c.st = stream_of(&o);
+    c.o = o;
+    c.o.stream = (void *)c.st;
+    c.o.validate = 0;
+    c.dep.assign(m, 0);
+    c.colperm.resize(n);
+    for (int64_t j = 0; j < n; ++j) c.colperm[j] = j;
+    if (o.validate) {
+        unsigned *bad = nullptr;
+        FF_HIP_CHECK(hipMalloc(&bad, sizeof(unsigned)));
+        unsigned h = 0;
+        hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned), c.st);
+        if (e == hipSuccess) e = launch_validate(A, lda, m, n, p, bad, c.st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, c.st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+        (void)hipFree(bad);
+        if (e != hipSuccess) return fail(FF_EHIP, std::string("validate: ") + hipGetErrorString(e));
+        if (h) return fail(FF_EINVAL, std::to_string(h) + " entries of A are not residues < p");
+    }
+    // scratch: U (r x n) and X^T (r x m) for r <= min(m, n), row lists,
+    // exchange pairs, panel results
+    const int64_t rmax = std::min(m, n);
+    const int64_t u_bytes = round_up(rmax * n * 4, 256), x_bytes = round_up(rmax * m * 4, 256);
+    const int64_t rows_bytes = round_up(m * 8, 256), pairs_bytes = round_up(2 * std::max<int64_t>(n, 64) * 8, 256);
+    const int64_t out_bytes = 1024, first_bytes = round_up(LQUP_PANEL * 8, 256);
+    void *ws = nullptr;
+    rc = workspace(c.st, (size_t)(u_bytes + x_bytes + rows_bytes + pairs_bytes + out_bytes + first_bytes),
+                   &ws, 2);
+    if (rc) return rc;
+    char *w = (char *)ws;
+    c.U = (uint32_t *)w;
+    c.Xt = (uint32_t *)(w + u_bytes);
+    c.d_rows = (int64_t *)(w + u_bytes + x_bytes);
+    c.d_pairs = (int64_t *)(w + u_bytes + x_bytes + rows_bytes);
+    c.d_out = (int32_t *)(w + u_bytes + x_bytes + rows_bytes + pairs_bytes);
+    c.d_first = (int64_t *)(w + u_bytes + x_bytes + rows_bytes + pairs_bytes + out_bytes);
+    int64_t found = 0;
+    rc = rec(c, 0, m, &found);
+    if (rc) return rc;
+    FF_HIP_CHECK(hipStreamSynchronize(c.st));
+    *rank = c.k;
+    int64_t d = 0;
+    for (int64_t v : c.piv) pivrows[d++] = v;
+    for (int64_t i = 0; i < m; ++i)
+        if (c.dep[i]) pivrows[d++] = i;
+    if (d != m) return fail(FF_EHIP, "internal error: rows not all classified");
+    for (int64_t j = 0; j < n; ++j) colperm[j] = c.colperm[j];
+    return FF_OK;
+}
+
+int ff_frank(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t *rank,
+             const ff_opts *opts)
+{
+    if (m < 0 || n < 0) return fail(FF_EINVAL, "negative dimension");
+    std::vector<int64_t> piv(std::max<int64_t>(m, 1)), perm(std::max<int64_t>(n, 1));
+    return ff_flqup(p, m, n, A, lda, rank, piv.data(), perm.data(), opts);
+}
+
+int ff_fdet(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *det, const ff_opts *opts)
+{
+    if (!det) return fail(FF_EINVAL, "null output pointer");
+    if (n < 0) return fail(FF_EINVAL, "negative dimension");
+    if (n == 0) {
+        *det = 1 % p;
+        return FF_OK;
+    }
+    std::vector<int64_t> piv(n), perm(n);
+    int64_t r = 0;
+    int rc = ff_flqup(p, n, n, A, lda, &r, piv.data(), perm.data(), opts);
+    if (rc) return rc;
+    if (r < n) {
+        *det = 0;
+        return FF_OK;
+    }
+    // every row is a pivot row, in order: det = sign(colperm) prod A[k][k]
+    ff_opts o = opts ? *opts : default_opts();
+    hipStream_t st = stream_of(&o);
+    std::vector<uint32_t> diag(n);
+    FF_HIP_CHECK(hipMemcpy2DAsync(diag.data(), 4, A, (size_t)(lda + 1) * 4, 4, (size_t)n,
+                                  hipMemcpyDeviceToHost, st));
+    FF_HIP_CHECK(hipStreamSynchronize(st));
+    uint64_t d = 1;
+    for (int64_t k = 0; k < n; ++k) d = d * diag[k] % p;
+    std::vector<char> seen(n, 0);
+    int sign = 1;
+    for (int64_t s = 0; s < n; ++s) {
+        if (seen[s]) continue;
+        int64_t len = 0;
+        for (int64_t j = s; !seen[j]; j = perm[j]) {
+            seen[j] = 1;
+            ++len;
+        }
+        if (len % 2 == 0) sign = -sign;
+    }
+    *det = (uint32_t)(sign > 0 ? d : (p - d) % p);
+    return FF_OK;
+}
+
+} // extern "C"

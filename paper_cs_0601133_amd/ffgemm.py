@@ -69,6 +69,9 @@ _SIGS = {
     "ff_ftrsm": ([_U32, _INT, _INT, _INT, _I64, _I64, _U32, _VP, _I64, _VP, _I64], _INT),
     "ff_ftrsm_ex": ([_U32, _INT, _INT, _INT, _I64, _I64, _U32, _VP, _I64, _VP, _I64,
                      ctypes.POINTER(ff_opts)], _INT),
+    "ff_flqup": ([_U32, _I64, _I64, _VP, _I64, _VP, _VP, _VP, ctypes.POINTER(ff_opts)], _INT),
+    "ff_frank": ([_U32, _I64, _I64, _VP, _I64, _VP, ctypes.POINTER(ff_opts)], _INT),
+    "ff_fdet": ([_U32, _I64, _VP, _I64, _VP, ctypes.POINTER(ff_opts)], _INT),
     "ff_plan_query": ([_U32, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ff_opts),
                        ctypes.POINTER(ff_plan_info)], _INT),
     "ff_fgemm_batched": ([ctypes.POINTER(ff_job), _INT, ctypes.POINTER(ff_opts)], _INT),
@@ -215,6 +218,24 @@ def ff_ftrsm_ex(p, uplo, transT, diag, m, n, alpha, T, ldt, B, ldb, opts=None):
                               o)
 
 
+def ff_flqup(p, m, n, A, lda, rank, pivrows, colperm, opts=None):
+    """rank, pivrows, colperm: numpy int64 arrays (host) of sizes 1, m, n."""
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_flqup(p, m, n, _addr(A), lda, rank.ctypes.data, pivrows.ctypes.data,
+                           colperm.ctypes.data, o)
+
+
+def ff_frank(p, m, n, A, lda, rank, opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_frank(p, m, n, _addr(A), lda, rank.ctypes.data, o)
+
+
+def ff_fdet(p, n, A, lda, det, opts=None):
+    """det: numpy uint32 array (host) of size 1."""
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_fdet(p, n, _addr(A), lda, det.ctypes.data, o)
+
+
 def ff_plan_query(p, transA, transB, m, n, k, opts=None):
     info = ff_plan_info()
     o = ctypes.byref(opts) if opts is not None else None
@@ -330,6 +351,35 @@ def ftrsm(p, T, B, alpha=1, lower=False, trans=False, unit=False, opts=None):
         opts.stream = _torch_stream()
     return _check(ff_ftrsm_ex(p, int(lower), int(trans), int(unit), m, n, alpha % p, T,
                               _ld(T, 1), B, _ld(B, 1), opts))
+
+
+def lqup(p, A, opts=None):
+    """LQUP of the torch tensor A (m x n, overwritten by the compressed form)
+    on torch's current stream; returns (rank, pivrows, colperm) as Python
+    int and numpy int64 arrays."""
+    import numpy as np
+    m, n = A.shape[0], A.shape[1]
+    if opts is None:
+        opts = make_opts()
+    if not opts.stream:
+        opts.stream = _torch_stream()
+    rank = np.zeros(1, dtype=np.int64)
+    piv = np.zeros(max(m, 1), dtype=np.int64)
+    perm = np.zeros(max(n, 1), dtype=np.int64)
+    _check(ff_flqup(p, m, n, A, _ld(A, 1), rank, piv, perm, opts))
+    return int(rank[0]), piv[:m], perm[:n]
+
+
+def det(p, A, opts=None):
+    """det of the square torch tensor A over Z/p (A is overwritten)."""
+    import numpy as np
+    if opts is None:
+        opts = make_opts()
+    if not opts.stream:
+        opts.stream = _torch_stream()
+    d = np.zeros(1, dtype=np.uint32)
+    _check(ff_fdet(p, A.shape[0], A, _ld(A, 1), d, opts))
+    return int(d[0])
 
 
 def fgemm(p, A, B, C, alpha=1, beta=0, transA=False, transB=False, opts=None):

@@ -1,0 +1,163 @@
+"""Parity of the HIP LQUP factorisation, rank and determinant with the CPU
+oracle (bit-exact).
+
+Under the pivoting rule both sides follow (rows in order, first nonzero
+column not yet used) the compressed factorisation, the pivot rows and the
+column permutation are unique, so they are compared element by element.
+At 2048 and 4096, where the oracle's elimination would take minutes, the
+factors must rebuild A on sampled entries computed by the oracle one by one
+and have the echelon structure; a valid factorisation certifies the rank
+and the determinant.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import from_dev, to_dev
+from paper_cs_0601133_amd import ffgemm as ff
+from paper_cs_0601133_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+PRIMES = [2, 3, 7, 65521, 8388593, 2147483647]
+
+
+def gpu_lqup(p, A, **opts):
+    dA = to_dev(A)
+    r, piv, perm = ff.lqup(p, dA, opts=ff.make_opts(**opts))
+    return from_dev(dA), r, piv, perm
+
+
+def assert_same(p, A, **opts):
+    F, r, piv, perm = gpu_lqup(p, A, **opts)
+    F0, r0, piv0, perm0 = oracle.lqup(p, A)
+    assert r == r0, (A.shape, r, r0)
+    assert np.array_equal(perm, perm0), A.shape
+    assert np.array_equal(piv, piv0), A.shape
+    assert np.array_equal(F, F0), A.shape
+    return r
+
+
+def known_rank(p, m, n, r, seed):
+    # X = [I_r; R1] (rows shuffled) times Y = [I_r R2] (columns shuffled)
+    rng = np.random.default_rng(seed)
+    X = np.zeros((m, r), np.uint32)
+    Y = np.zeros((r, n), np.uint32)
+    X[:r] = np.eye(r, dtype=np.uint32)
+    X[r:] = synth.residues(synth.seed_for(seed, 1), (m - r, r), p)
+    Y[:, :r] = np.eye(r, dtype=np.uint32)
+    Y[:, r:] = synth.residues(synth.seed_for(seed, 2), (r, n - r), p)
+    return oracle.fgemm(p, np.ascontiguousarray(X[rng.permutation(m)]),
+                        np.ascontiguousarray(Y[:, rng.permutation(n)]))
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_random_matrices_match_the_oracle(p):
+    # shapes spanning several panels, ragged ones, and windows narrower
+    # than the remaining columns
+    for si, (m, n) in enumerate([(1, 1), (5, 3), (3, 5), (64, 64), (65, 70), (130, 100),
+                                  (100, 300), (300, 290)]):
+        A = synth.residues(synth.seed_for(140 + si, 1), (m, n), p)
+        assert_same(p, A)
+
+
+@pytest.mark.parametrize("p", [7, 8388593, 2147483647])
+def test_constructed_ranks_match_the_oracle(p):
+    for si, (m, n, r) in enumerate([(100, 80, 0), (100, 80, 1), (100, 80, 37), (200, 600, 30),
+                                     (150, 150, 149), (300, 120, 120)]):
+        A = known_rank(p, m, n, r, 150 + si)
+        assert assert_same(p, A) == r, (m, n, r)
+
+
+def test_pivots_past_the_window():
+    # row i has its only nonzero at column 400 + 3i: every panel row must
+    # search past the 256-column window; rows 7 and 8 repeat rows 1 and 2
+    p, m, n = 65521, 12, 600
+    A = np.zeros((m, n), np.uint32)
+    for i in range(m):
+        A[i, 400 + 3 * i] = 1 + i
+    A[7] = 2 * A[1] % p
+    A[8] = 5 * A[2] % p
+    assert_same(p, A)
+    # a dense block below such rows
+    B = np.vstack([A, synth.residues(synth.seed_for(160, 1), (70, n), p)])
+    assert_same(p, B)
+
+
+def test_update_paths():
+    p, m, n = 8388593, 260, 300
+    A = synth.residues(synth.seed_for(161, 1), (m, n), p)
+    assert_same(p, A, path=ff.FF_PATH_FP64)
+    assert_same(p, A, path=ff.FF_PATH_INT8)
+
+
+def test_rank_and_det():
+    import torch
+    for p in (7, 65521, 2147483647):
+        for si, n in enumerate((1, 2, 17, 130)):
+            A = synth.residues(synth.seed_for(170 + si, 1), (n, n), p)
+            d = ff.det(p, to_dev(A))
+            assert d == oracle.det(p, A), (p, n)
+        S = known_rank(p, 90, 90, 89, 175)
+        assert ff.det(p, to_dev(S)) == 0
+        rank = np.zeros(1, np.int64)
+        R = known_rank(p, 90, 140, 61, 176)
+        dR = to_dev(R)
+        assert ff.ff_frank(p, 90, 140, dR, 140, rank) == ff.FF_OK and rank[0] == 61
+    d = np.zeros(1, np.uint32)
+    assert ff.ff_fdet(7, 0, to_dev(np.zeros((1, 1), np.uint32)), 1, d) == ff.FF_OK and d[0] == 1
+    torch.cuda.synchronize()
+
+
+def test_arguments_and_empty_shapes():
+    p = 7
+    rank = np.zeros(1, np.int64)
+    piv = np.zeros(4, np.int64)
+    perm = np.zeros(4, np.int64)
+    dA = to_dev(np.ones((4, 4), np.uint32))
+    assert ff.ff_flqup(p, 4, 4, dA, 3, rank, piv, perm) == ff.FF_EINVAL   # lda < n
+    assert ff.ff_flqup(1, 4, 4, dA, 4, rank, piv, perm) == ff.FF_EINVAL   # p < 2
+    assert ff.ff_flqup(p, 0, 4, dA, 4, rank, piv, perm) == ff.FF_OK and rank[0] == 0
+    assert list(perm) == [0, 1, 2, 3]
+    # validate rejects entries >= p and writes nothing
+    bad = np.ones((4, 4), np.uint32)
+    bad[2, 3] = p
+    dB = to_dev(bad)
+    assert ff.ff_flqup(p, 4, 4, dB, 4, rank, piv, perm, ff.make_opts(validate=1)) == ff.FF_EINVAL
+    assert np.array_equal(from_dev(dB), bad)
+
+
+def check_certificate(p, A, F, r, piv, perm, samples, seed):
+    m, n = A.shape
+    assert sorted(piv) == list(range(m)) and sorted(perm) == list(range(n))
+    is_piv = np.zeros(m, bool)
+    is_piv[piv[:r]] = True
+    above = np.concatenate(([0], np.cumsum(is_piv)[:-1]))
+    for i in range(m):
+        ka = int(above[i])
+        if is_piv[i]:
+            assert F[i, ka] != 0, i
+        else:
+            assert not F[i, ka:].any(), i
+    L, QU = oracle.lqup_factors(p, F, r, piv)
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, m, samples)
+    cols = rng.integers(0, n, samples)
+    lhs = oracle.fgemm_entries(p, L, QU, rows, cols)
+    assert np.array_equal(lhs, A[:, perm][rows, cols])
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_full_size_certificate(n):
+    # m = n = 4096, p = 8388593 is the benchmark's launch configuration
+    p = 8388593
+    A = synth.residues(synth.seed_for(180 + n, 1), (n, n), p)
+    F, r, piv, perm = gpu_lqup(p, A)
+    assert r == n
+    check_certificate(p, A, F, r, piv, perm, 600, 5)
+    # rank deficient at full width: rank n / 2
+    if n == 2048:
+        R = known_rank(p, n, n, n // 2, 181)
+        F, r, piv, perm = gpu_lqup(p, R)
+        assert r == n // 2
+        check_certificate(p, R, F, r, piv, perm, 600, 6)
