@@ -15,8 +15,8 @@ digit GEMM, timed with HIP events around its launches), the CPU oracle timed
 on a bounded sample of the same product, and the other workloads: the
 n = 256 latency case, n = 8192 at p = 251 and with Winograd levels, the
 64-job multi-modular batch (plain, persistent and graph-replayed), the
-triangular solve with matrix right-hand side (Section 4) and the Poisson
-serving stream.
+triangular solve with matrix right-hand side (Section 4), the LQUP
+factorisation (Section 5.1) and the Poisson serving stream.
 """
 import argparse
 import hashlib
@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the 4096^3 workload (profiler runs)")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--ftrsm-only", action="store_true",
+                    help="time only the triangular solves (profiler runs)")
+    ap.add_argument("--lqup-only", action="store_true",
+                    help="time only the LQUP factorisations (profiler runs)")
     return ap.parse_args()
 
 
@@ -311,6 +315,31 @@ def triangular_solve(torch, ff, args):
     return out
 
 
+def factorisation(torch, ff, args):
+    """LQUP (Section 5.1) of a seeded dense n x n matrix of residues, in
+    place; each step restores A from a device copy first (a 4 n^2-byte copy,
+    under 0.2% of the step).  Throughput is (2/3) n^3 / t, the operation
+    count of the factorisation with classical products (Section 5)."""
+    from paper_cs_0601133_amd import synth
+    out = {}
+    for n, p in ((4096, 8388593), (4096, 65521), (8192, 8388593)):
+        A = synth.residues(0x5EED0000 + 8000 + n, (n, n), p)
+        dA0 = torch.from_numpy(A.view(np.int32)).cuda()
+        dA = torch.empty_like(dA0)
+        del A
+        ranks = []
+
+        def step():
+            dA.copy_(dA0)
+            ranks.append(ff.lqup(p, dA)[0])
+        ms, _, _ = time_calls(torch, step, 3, 1)
+        out[f"n{n}_p{p}"] = {"ms": ms, "rank": ranks[-1],
+                             "gops_2n3_3": 2.0 * n ** 3 / 3.0 / ms / 1e6}
+        log(f"lqup n={n} p={p}: {ms:.2f} ms, rank {ranks[-1]}")
+        del dA, dA0
+    return out
+
+
 def serving(torch, ff, args):
     nreq = args.serve_requests
     rng = np.random.default_rng(5)
@@ -376,6 +405,12 @@ def main():
 
     torch.cuda.set_device(0)
     ff.ff_init()
+    if args.ftrsm_only:
+        print(json.dumps({"workloads": {"ftrsm": triangular_solve(torch, ff, args)}}))
+        return
+    if args.lqup_only:
+        print(json.dumps({"workloads": {"lqup": factorisation(torch, ff, args)}}))
+        return
     paths, (A, B, C) = headline(torch, ff, args)
     head = paths["int8_d7"]
     ops = 2.0 * M * N * K
@@ -418,6 +453,7 @@ def main():
             "n8192": large_8192(torch, ff, args),
             "multimodular_64_jobs": multimodular(torch, ff, args),
             "ftrsm": triangular_solve(torch, ff, args),
+            "lqup": factorisation(torch, ff, args),
             "serving": serving(torch, ff, args),
         }
     if not args.no_cpu:

@@ -207,17 +207,17 @@ hipError_t launch_i8_batched(int tile, const I8Job *dev_jobs, int njobs,
 // Triangular solve (kernels_trsm.hip): the block recursion stops at leaves
 // of at most TRSM_LEAF_MAX rows (a multiple of 64), solved by one kernel.
 constexpr int TRSM_LEAF_MAX = 512;
-// dinv_i = op(T)_ii^-1 mod p (1 when unit), *bad counts diagonal entries with
-// no inverse.
+// dinv_i = op(T)_ii^-1 mod p (1 when unit); bad (may be null) counts
+// diagonal entries with no inverse.
 hipError_t launch_trsm_dinv(const uint32_t *T, int64_t ldt, int64_t m, uint32_t p, int unit,
                             uint32_t *dinv, unsigned *bad, hipStream_t st);
-// Tn = D^-1 op(T) restricted to its triangle (lower: op(T) lower), unit
+// Tn = D^-1 op(T) (dinv null: D = I) restricted to its triangle (lower: op(T) lower), unit
 // diagonal, zero elsewhere; ldn x ldn row-major (ldn = m rounded up to a
 // multiple of 64, padding = identity).
 hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower, int64_t m,
                             int64_t ldn, uint32_t p, const uint32_t *dinv, uint32_t *Tn,
                             hipStream_t st);
-// B(i, :) <- alpha dinv_i B(i, :) mod p.
+// B(i, :) <- alpha dinv_i B(i, :) mod p (dinv null: all ones).
 hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uint32_t p,
                              uint32_t alpha, const uint32_t *dinv, hipStream_t st);
 // Tinv[g] = inverse of the 64 x 64 diagonal block g of Tn, g < ldn / 64

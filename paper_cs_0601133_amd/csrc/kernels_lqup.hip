@@ -69,13 +69,16 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
                                                    int64_t k, int W, int whole, uint32_t p,
                                                    double pinv, int32_t *out)
 {
-    __shared__ double s_row[PW];       // pivot row, published
-    __shared__ double s_col[PR];       // column t, published
+    // published pivot row, column t and search results, double-buffered by
+    // row parity so that a row's writes never meet the previous row's reads
+    // (two barriers per row instead of three)
+    __shared__ double s_row[2][PW];
+    __shared__ double s_col[2][PR];
     __shared__ double s_swap[2][PR];   // column exchange
     __shared__ uint32_t s_piv[PR];     // pivot values (fraction-free, canonical)
     __shared__ uint32_t s_inv[PR];     // their inverses
     __shared__ uint32_t s_invS[PR + 1]; // inverse scale after j pivots
-    __shared__ int s_first[PW / 64];
+    __shared__ int s_first[2][PW / 64];
     __shared__ int s_rowpiv[PR];       // pivot index of a row, -1 dependent, -2 untouched
     __shared__ int s_before[PR];       // pivots above the row when it was processed
     const int tid = threadIdx.x, lane = tid & 63;
@@ -104,18 +107,18 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
 #pragma unroll
     for (int r = 0; r < PR; ++r) {
         if (stuck || r >= nr) continue;
-        const int gr = r / PQ, qr = r % PQ;
+        const int gr = r / PQ, qr = r % PQ, pb = r & 1;
         // row r: publish it, and find its first nonzero at or after column t
         if (g == gr) {
-            s_row[c] = v[qr];
+            s_row[pb][c] = v[qr];
             const bool nz = c >= t && c < W && v[qr] != 0.0;
             const uint64_t bal = __ballot(nz);
-            if (lane == 0) s_first[c / 64] = bal ? (c - lane) + __builtin_ctzll(bal) : PW;
+            if (lane == 0) s_first[pb][c / 64] = bal ? (c - lane) + __builtin_ctzll(bal) : PW;
         }
         __syncthreads();
         int cmin = PW;
 #pragma unroll
-        for (int ww = 0; ww < PW / 64; ++ww) cmin = min(cmin, s_first[ww]);
+        for (int ww = 0; ww < PW / 64; ++ww) cmin = min(cmin, s_first[pb][ww]);
         if (cmin >= PW) {
             if (!whole) {
                 stuck = 1;
@@ -123,7 +126,6 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
                 if (tid == 0) { s_rowpiv[r] = -1; s_before[r] = t; }
                 ++nproc; // dependent row: zero from column t on
             }
-            __syncthreads(); // s_first and s_row are rewritten by the next row
             continue;
         }
         if (cmin != t) {
@@ -145,12 +147,12 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
 #pragma unroll
                 for (int q = 0; q < PQ; ++q) v[q] = s_swap[0][r0g + q];
             }
-            if (g == gr && (c == t || c == cmin)) s_row[c] = v[qr];
+            if (g == gr && (c == t || c == cmin)) s_row[pb][c] = v[qr];
         }
         // publish column t (the pivot and the entries below it)
         if (c == t) {
 #pragma unroll
-            for (int q = 0; q < PQ; ++q) s_col[r0g + q] = v[q];
+            for (int q = 0; q < PQ; ++q) s_col[pb][r0g + q] = v[q];
         }
         if (tid == 0) {
             s_rowpiv[r] = t;
@@ -158,19 +160,19 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
             out[3 + PR + t] = cmin;
         }
         __syncthreads();
-        const double pv = s_col[r];
+        const double pv = s_col[pb][r];
         if (tid == 0) {
             const double pc = EXACT ? (pv < 0 ? pv + pd : pv) : pv;
             s_piv[t] = (uint32_t)pc;
         }
         // rows below r, columns after t (groups entirely above r skip)
         if (g >= gr && c > t && c < W) {
-            const double y = s_row[c];
+            const double y = s_row[pb][c];
 #pragma unroll
             for (int q = 0; q < PQ; ++q) {
                 const int r2 = r0g + q;
                 if (r2 > r && r2 < nr) {
-                    const double a = s_col[r2];
+                    const double a = s_col[pb][r2];
                     if (EXACT) {
                         v[q] = reduce_c(__builtin_fma(pv, v[q], -a * y), pd, pinv);
                     } else {
@@ -183,8 +185,8 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
         }
         ++t;
         ++nproc;
-        __syncthreads(); // s_row, s_col and s_first are rewritten by the next row
     }
+    __syncthreads();
     // inverses of the pivots, and of the scales S_j = pi_0 ... pi_{j-1}
     if (tid < t) s_inv[tid] = inv_mod(s_piv[tid], p);
     __syncthreads();

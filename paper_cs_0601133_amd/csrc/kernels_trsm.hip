@@ -49,12 +49,13 @@ __global__ __launch_bounds__(TT) void k_trsm_dinv(const uint32_t *T, int64_t ldt
     uint32_t d = 1;
     if (!unit) {
         d = inv_mod(T[i * ldt + i], p);
-        if (d == 0) atomicAdd(bad, 1u);
+        if (d == 0 && bad) atomicAdd(bad, 1u);
     }
     dinv[i] = d;
 }
 
-// T'(i, j) = dinv_i op(T)(i, j) inside the triangle (i, j < m), 1 on the
+// T'(i, j) = dinv_i op(T)(i, j) (dinv null: unit diagonal, all ones) inside
+// the triangle (i, j < m), 1 on the
 // whole diagonal, 0 elsewhere; ldn x ldn row-major, ldn = m rounded up to a
 // multiple of 64, so that every 64-row block is whole and its padding rows
 // and columns are those of the identity.  One workgroup per 64 x 64 tile:
@@ -93,12 +94,13 @@ __global__ __launch_bounds__(TT) void k_trsm_prep(const uint32_t *T, int64_t ldt
         const int64_t i = i0 + r, j = j0 + c;
         uint32_t v = 0;
         if (i == j) v = 1;
-        else if (i < m && j < m && (lower ? j < i : j > i)) v = mulmod(dinv[i], tile[r][c], p, pinv);
+        else if (i < m && j < m && (lower ? j < i : j > i))
+            v = dinv ? mulmod(dinv[i], tile[r][c], p, pinv) : tile[r][c];
         dst[(int64_t)r * ldn + c] = v;
     }
 }
 
-// B(i, j) <- alpha dinv_i B(i, j) mod p: workgroup (x, y) scales 1024
+// B(i, j) <- alpha dinv_i B(i, j) mod p (dinv null: all ones): workgroup (x, y) scales 1024
 // columns of rows y, y + gridDim.y, ...
 __global__ __launch_bounds__(TT) void k_trsm_scale(uint32_t *B, int64_t ldb, int64_t m,
                                                    int64_t n, uint32_t p, double pinv,
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(TT) void k_trsm_scale(uint32_t *B, int64_t ldb, int
 {
     const int64_t j0 = (int64_t)blockIdx.x * 4 * TT + threadIdx.x;
     for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
-        const uint32_t f = mulmod(alpha, dinv[i], p, pinv);
+        const uint32_t f = dinv ? mulmod(alpha, dinv[i], p, pinv) : alpha;
         uint32_t *row = B + i * ldb;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -128,74 +130,74 @@ __device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 // upper: l = 63, 62, ..) y_l is final once the rows before it have been
 // subtracted, and is then subtracted, times T'(i, l), from every other row
 // (T' is read with its diagonal set to 0, and it is 0 on the far side of the
-// triangle, so no row needs a test).  A workgroup takes 16 columns of one
-// block; a thread keeps rows (tid / 16) + 16 r, r < 4, of its column in
-// registers, unreduced: each is a sum of at most 63 products of centered
-// values, exact in binary64 under the bound of the leaf solve (SPLIT: the
-// entries of T' cut in two as there).  The owner of row l publishes it,
-// reduced, through a two-slot LDS row, one barrier per step.
-template <bool SPLIT>
-__global__ __launch_bounds__(TT) void k_trsm_inv(const uint32_t *Tn, int64_t ldn, int lower,
-                                                 uint32_t p, double pinv, uint32_t *Tinv)
+// triangle, so no row needs a test).  One wave takes 16 columns of one
+// block; lane (j, rl) keeps rows rl + 4q, q < 16, of its column in registers,
+// unreduced: each is a sum of at most 63 products of centered values, exact
+// in binary64 under the bound of the leaf solve (SPLIT: the entries of T'
+// cut in two as there).  Row l, reduced, reaches the lanes of its column by
+// a shuffle: no barrier inside the 64 steps.
+template <bool SPLIT, bool LOWER>
+__global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn, uint32_t p,
+                                                 double pinv, uint32_t *Tinv)
 {
-    __shared__ double sT[SPLIT ? 2 : 1][64][64]; // sT[.][l][i] = T'(i, l), diagonal 0
-    __shared__ double sRow[2][16];
+    // sT[.][l][i] = T'(i, l), diagonal 0; rows padded to 65 so that the
+    // transposing stores (one l per lane) spread over the banks
+    __shared__ double sT[SPLIT ? 2 : 1][64][65];
     const int g = blockIdx.x >> 2, jq = blockIdx.x & 3;
-    const int jl = threadIdx.x & 15, il = threadIdx.x >> 4;
+    const int lane = threadIdx.x, jl = lane & 15, rl = lane >> 4;
     const int j = 16 * jq + jl;
     const uint32_t half = (p - 1) / 2;
     const double pd = (double)p;
     const uint32_t *src = Tn + (int64_t)64 * g * ldn + 64 * g;
-    for (int e = threadIdx.x; e < 64 * 64; e += TT) {
-        const int i = e >> 6, l = e & 63;
-        const double t = i == l ? 0.0 : (double)center(src[(int64_t)i * ldn + l], p, half);
+    uint32_t raw[64]; // row i, column l = lane: all loads in flight at once
+#pragma unroll
+    for (int i = 0; i < 64; ++i) raw[i] = src[(int64_t)i * ldn + lane];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        const double t = i == lane ? 0.0 : (double)center(raw[i], p, half);
         if (SPLIT) {
             const double th = __builtin_rint(t * (1.0 / 32768.0));
-            sT[0][l][i] = th;
-            sT[SPLIT ? 1 : 0][l][i] = __builtin_fma(-th, 32768.0, t);
+            sT[0][lane][i] = th;
+            sT[SPLIT ? 1 : 0][lane][i] = __builtin_fma(-th, 32768.0, t);
         } else {
-            sT[0][l][i] = t;
+            sT[0][lane][i] = t;
         }
     }
-    double y[4], yh[4];
+    double y[16], yh[16];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        y[r] = il + 16 * r == j ? 1.0 : 0.0;
-        yh[r] = 0.0;
+    for (int q = 0; q < 16; ++q) {
+        y[q] = rl + 4 * q == j ? 1.0 : 0.0;
+        yh[q] = 0.0;
     }
     __syncthreads();
+#pragma unroll
     for (int s = 0; s < 64; ++s) {
-        const int l = lower ? s : 63 - s;
-        if (il == (l & 15)) {
+        const int l = LOWER ? s : 63 - s;
+        const int qo = l >> 2, ro = l & 3;
+        // every lane reduces its entry q = qo (a value-preserving step); the
+        // lane with rl == ro holds row l, now final
+        double v = y[qo];
+        if (SPLIT) v = __builtin_fma(reduce_c(yh[qo], pd, pinv), 32768.0, v);
+        v = reduce_c(v, pd, pinv);
+        y[qo] = v;
+        yh[qo] = 0.0;
+        const double yl = __shfl(v, jl + 16 * ro, 64);
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (r == (l >> 4)) {
-                    double v = y[r];
-                    if (SPLIT) v = __builtin_fma(reduce_c(yh[r], pd, pinv), 32768.0, v);
-                    v = reduce_c(v, pd, pinv);
-                    y[r] = v;
-                    yh[r] = 0.0;
-                    sRow[s & 1][jl] = v;
-                }
-        }
-        __syncthreads();
-        const double yl = sRow[s & 1][jl];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = il + 16 * r;
+        for (int q = 0; q < 16; ++q) {
+            const int i = rl + 4 * q;
             if (SPLIT) {
-                yh[r] = __builtin_fma(-sT[0][l][i], yl, yh[r]);
-                y[r] = __builtin_fma(-sT[SPLIT ? 1 : 0][l][i], yl, y[r]);
+                yh[q] = __builtin_fma(-sT[0][l][i], yl, yh[q]);
+                y[q] = __builtin_fma(-sT[SPLIT ? 1 : 0][l][i], yl, y[q]);
             } else {
-                y[r] = __builtin_fma(-sT[0][l][i], yl, y[r]);
+                y[q] = __builtin_fma(-sT[0][l][i], yl, y[q]);
             }
         }
     }
-    // every row was reduced when it was published (its later updates add
+    // every row was reduced when it became final (its later updates add
     // T'(i, l) = 0 terms only)
     uint32_t *dst = Tinv + (int64_t)4096 * g;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dst[(il + 16 * r) * 64 + j] = canon_f64(y[r], pd, pinv, p);
+    for (int q = 0; q < 16; ++q) dst[(rl + 4 * q) * 64 + j] = canon_f64(y[q], pd, pinv, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,12 +454,15 @@ hipError_t launch_trsm_inv(const uint32_t *Tn, int64_t ldn, int lower, uint32_t 
                            uint32_t *Tinv, hipStream_t st)
 {
     const dim3 grid((unsigned)(ldn / 64 * 4));
-    if (split)
-        hipLaunchKernelGGL(k_trsm_inv<true>, grid, dim3(TT), 0, st, Tn, ldn, lower, p,
-                           1.0 / (double)p, Tinv);
+    const double pinv = 1.0 / (double)p;
+    if (split && lower)
+        hipLaunchKernelGGL((k_trsm_inv<true, true>), grid, dim3(64), 0, st, Tn, ldn, p, pinv, Tinv);
+    else if (split)
+        hipLaunchKernelGGL((k_trsm_inv<true, false>), grid, dim3(64), 0, st, Tn, ldn, p, pinv, Tinv);
+    else if (lower)
+        hipLaunchKernelGGL((k_trsm_inv<false, true>), grid, dim3(64), 0, st, Tn, ldn, p, pinv, Tinv);
     else
-        hipLaunchKernelGGL(k_trsm_inv<false>, grid, dim3(TT), 0, st, Tn, ldn, lower, p,
-                           1.0 / (double)p, Tinv);
+        hipLaunchKernelGGL((k_trsm_inv<false, false>), grid, dim3(64), 0, st, Tn, ldn, p, pinv, Tinv);
     return hipGetLastError();
 }
 

@@ -141,18 +141,24 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
     uint32_t *dinv = (uint32_t *)((char *)wsv + tn_bytes + ti_bytes);
     unsigned *bad = (unsigned *)((char *)wsv + tn_bytes + ti_bytes + di_bytes);
     const int lower = (uplo == FF_LOWER) ^ (transT == FF_TRANS);
-    FF_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), st));
-    FF_HIP_CHECK(launch_trsm_dinv(T, ldt, m, p, diag == FF_UNIT, dinv, bad, st));
-    if (o.validate && diag != FF_UNIT) {
-        unsigned h = 0;
-        FF_HIP_CHECK(hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-        FF_HIP_CHECK(hipStreamSynchronize(st));
-        if (h)
-            return fail(FF_EINVAL,
-                        std::to_string(h) + " diagonal entries of T have no inverse modulo p");
+    // a unit diagonal needs no inverses (dinv stays null for the kernels);
+    // the flag that counts non-invertible entries is only read by validate
+    const bool unit = diag == FF_UNIT;
+    if (!unit) {
+        if (o.validate) FF_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), st));
+        FF_HIP_CHECK(launch_trsm_dinv(T, ldt, m, p, 0, dinv, o.validate ? bad : nullptr, st));
+        if (o.validate) {
+            unsigned h = 0;
+            FF_HIP_CHECK(hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+            FF_HIP_CHECK(hipStreamSynchronize(st));
+            if (h)
+                return fail(FF_EINVAL,
+                            std::to_string(h) + " diagonal entries of T have no inverse modulo p");
+        }
     }
-    FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, ldn, p, dinv, Tn, st));
-    if (alpha != 1 || diag != FF_UNIT) FF_HIP_CHECK(launch_trsm_scale(B, ldb, m, n, p, alpha, dinv, st));
+    const uint32_t *dv = unit ? nullptr : dinv;
+    FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, ldn, p, dv, Tn, st));
+    if (alpha != 1 || !unit) FF_HIP_CHECK(launch_trsm_scale(B, ldb, m, n, p, alpha, dv, st));
     Trsm c;
     c.p = p;
     c.lower = lower;
