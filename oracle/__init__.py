@@ -12,6 +12,8 @@ Contents
   reduction after every multiply-add).
 * ``ftrsm``: the triangular solve op(T) X = alpha B mod p of Section 4 by
   plain substitution, every multiply-add reduced.
+* ``aat``: the symmetric product alpha A diag(d) A^T + beta C of Section 6
+  (lower triangle, mirrored), as the definition through ``fgemm``.
 * ``lqup`` / ``lqup_factors`` / ``det``: the LQUP factorisation of Section
   5.1 by plain row-by-row elimination (first nonzero column as pivot), its
   explicit factors, and the determinant read off U (Section 6).
@@ -287,3 +289,20 @@ def det(p, A, plant=None):
     for k in range(n):
         d = d * int(F[k, k]) % p
     return d if permutation_sign(perm) > 0 else (p - d) % p
+
+
+def aat(p, A, d=None, alpha=1, beta=0, C=None):
+    """Symmetric product of Section 6: the lower triangle (i >= j) of
+    alpha A diag(d) A^T + beta C mod p, mirrored into the upper triangle
+    (d None: the identity; C None: zeros).  Written as the definition
+    through fgemm with op(B) = (A diag(d))^T."""
+    A = np.ascontiguousarray(A, dtype=np.uint32)
+    m, k = A.shape
+    if d is None:
+        AD = A
+    else:
+        dd = np.asarray(d, dtype=np.uint64).reshape(1, k)
+        AD = np.ascontiguousarray((A.astype(np.uint64) * dd % p).astype(np.uint32))
+    C0 = np.zeros((m, m), np.uint32) if C is None else np.array(C, dtype=np.uint32)
+    R = fgemm(p, A, AD, C0, alpha, beta, transB=True)
+    return np.tril(R) + np.tril(R, -1).T
