@@ -16,7 +16,8 @@ on a bounded sample of the same product, and the other workloads: the
 n = 256 latency case, n = 8192 at p = 251 and with Winograd levels, the
 64-job multi-modular batch (plain, persistent and graph-replayed), the
 triangular solve with matrix right-hand side (Section 4), the LQUP
-factorisation (Section 5.1) and the Poisson serving stream.
+factorisation (Section 5.1), the symmetric product A D A^T (Section 6) and
+the Poisson serving stream.
 """
 import argparse
 import hashlib
@@ -57,6 +58,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--ftrsm-only", action="store_true",
                     help="time only the triangular solves (profiler runs)")
+    ap.add_argument("--aat-only", action="store_true",
+                    help="time only the symmetric product (profiler runs)")
     ap.add_argument("--lqup-only", action="store_true",
                     help="time only the LQUP factorisations (profiler runs)")
     return ap.parse_args()
@@ -315,6 +318,36 @@ def triangular_solve(torch, ff, args):
     return out
 
 
+def symmetric_product(torch, ff, args):
+    """C <- A diag(D) A^T mod p (Section 6) for m = k = 4096 and 8192,
+    p = 8388593, seeded A and D (and without D), next to fgemm computing
+    the same product in full (A' A^T with A' = A diag(D) precomputed).
+    Throughput is reported as 2 m^2 k / t (what the full product does); the
+    symmetric product's classical count is half of it (Section 6)."""
+    from paper_cs_0601133_amd import synth
+    p = P
+    out = {}
+    for m in (4096, 8192):
+        k = m
+        A = synth.residues(0x5EED0000 + 9000 + m, (m, k), p)
+        d = synth.residues(0x5EED0000 + 9001 + m, (k,), p)
+        AD = (A.astype(np.uint64) * d.astype(np.uint64)[None, :] % p).astype(np.uint32)
+        dA = torch.from_numpy(A.view(np.int32)).cuda()
+        dD = torch.from_numpy(d.view(np.int32)).cuda()
+        dAD = torch.from_numpy(AD.view(np.int32)).cuda()
+        dC = torch.zeros((m, m), dtype=torch.int32, device="cuda")
+        del A, AD
+        ms, _, _ = time_calls(torch, lambda: ff.aat(p, dA, dC, dD), 10, 2)
+        ms_nod, _, _ = time_calls(torch, lambda: ff.aat(p, dA, dC), 10, 2)
+        ms_full, _, _ = time_calls(torch, lambda: ff.fgemm(p, dA, dAD, dC, transB=True), 10, 2)
+        out[f"m{m}_k{k}"] = {"p": p, "ms": ms, "ms_without_D": ms_nod, "ms_fgemm_full": ms_full,
+                             "speedup_vs_fgemm": ms_full / ms,
+                             "gops_2m2k": 2.0 * m * m * k / ms / 1e6}
+        log(f"aat m=k={m}: {ms:.3f} ms ({ms_nod:.3f} without D; full fgemm {ms_full:.3f} ms)")
+        del dA, dD, dAD, dC
+    return out
+
+
 def factorisation(torch, ff, args):
     """LQUP (Section 5.1) of a seeded dense n x n matrix of residues, in
     place; each step restores A from a device copy first (a 4 n^2-byte copy,
@@ -408,6 +441,9 @@ def main():
     if args.ftrsm_only:
         print(json.dumps({"workloads": {"ftrsm": triangular_solve(torch, ff, args)}}))
         return
+    if args.aat_only:
+        print(json.dumps({"workloads": {"aat": symmetric_product(torch, ff, args)}}))
+        return
     if args.lqup_only:
         print(json.dumps({"workloads": {"lqup": factorisation(torch, ff, args)}}))
         return
@@ -454,6 +490,7 @@ def main():
             "multimodular_64_jobs": multimodular(torch, ff, args),
             "ftrsm": triangular_solve(torch, ff, args),
             "lqup": factorisation(torch, ff, args),
+            "aat": symmetric_product(torch, ff, args),
             "serving": serving(torch, ff, args),
         }
     if not args.no_cpu:

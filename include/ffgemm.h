@@ -210,6 +210,22 @@ int ff_frank(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
 int ff_fdet(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *det,
             const ff_opts *opts);
 
+/* Symmetric product (Section 6: A x A^T, "with a diagonal in the middle"):
+ *
+ *     C <- alpha A diag(D) A^T + beta C   (mod p).
+ *
+ * A is m x k (lda >= k), D a device vector of k residues or NULL (the
+ * identity), C m x m (ldc >= m); all device pointers owned by the caller,
+ * C not overlapping A or D.  The result is symmetric, so only its lower
+ * triangle is computed (about half the work of ff_fgemm_ex on the same
+ * shape) and then mirrored: on return C is symmetric, and the result
+ * depends only on the lower triangle (i >= j) of C on entry.  Arithmetic
+ * path, asynchrony and validate (A, D and C checked) as in ff_fgemm_ex;
+ * Winograd levels are not used.  Workspace: the operands' digit planes or
+ * packed doubles (once each), plus m k 4 bytes for A diag(D). */
+int ff_faat(uint32_t p, int64_t m, int64_t k, uint32_t alpha, const uint32_t *A, int64_t lda,
+            const uint32_t *D, uint32_t beta, uint32_t *C, int64_t ldc, const ff_opts *opts);
+
 /* The plan ff_fgemm_ex would follow for these sizes (host-only). */
 int ff_plan_query(uint32_t p, int transA, int transB,
                   int64_t m, int64_t n, int64_t k,

@@ -200,6 +200,10 @@ hipError_t launch_slice_batched(const SliceJob *dev_jobs, int njobs,
                                 int total_blocks, hipStream_t st);
 
 hipError_t launch_i8(int tile, const I8Job &job, hipStream_t st);
+// A device job table whose jobs all have the tile's digit count: one
+// workgroup per tile, no persistent queue.
+hipError_t launch_i8_jobs(int tile, const I8Job *dev_jobs, int njobs, int total_tiles,
+                          hipStream_t st);
 hipError_t launch_i8_batched(int tile, const I8Job *dev_jobs, int njobs,
                              int total_tiles, int persistent, unsigned *ctr,
                              hipStream_t st);
@@ -253,6 +257,12 @@ hipError_t launch_lqup_transpose(const uint32_t *src, int64_t lds, int64_t rows,
 // out[r] = first c in [c0, n) with A[i0 + r][c] != 0, or -1, for r < nr.
 hipError_t launch_lqup_first_nonzero(const uint32_t *A, int64_t lda, int64_t i0, int64_t nr,
                                      int64_t c0, int64_t n, int64_t *out, hipStream_t st);
+
+// Symmetric product (kernels_aat.hip): AD = A diag(d) mod p (m x k), and the
+// mirror C[r][c] = C[c][r] for r < c < m.
+hipError_t launch_aat_scale_cols(const uint32_t *A, int64_t lda, const uint32_t *d, int64_t m,
+                                 int64_t k, uint32_t p, uint32_t *AD, int64_t ldd, hipStream_t st);
+hipError_t launch_aat_mirror(uint32_t *C, int64_t ldc, int64_t m, hipStream_t st);
 
 // C <- (alpha * sum_s part[s] + beta*C) mod p over nsplit partial products
 // part[s][m][n] in [0, p).

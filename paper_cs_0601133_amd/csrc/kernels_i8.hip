@@ -383,6 +383,37 @@ void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
     }
 }
 
+// A job table whose jobs all have S digits (the symmetric product's block
+// rows): one workgroup per tile, tiles renumbered so that neighbours in a
+// job's tile order share an XCD, and only the S-digit tile body compiled
+// (the general table kernel's dispatch over digit counts costs registers).
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
+                          amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
+void k_fgemm_i8_jobs(const I8Job *__restrict__ jobs, int njobs, int total)
+{
+    using R = Ring<S, TM, TN, WGM, WGN, KS>;
+    __shared__ __attribute__((aligned(1024))) char smem[R::BYTES];
+    const int g = xcd_remap((int)blockIdx.x, total);
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_start <= g) lo = mid; else hi = mid - 1;
+    }
+    const I8Job J = jobs[lo];
+    int tm, tn;
+    grouped_tile_rt(g - J.tile_start, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
+    i8_tile<S, TM, TN, WGM, WGN, KS, R::NST, PIPE>(J, tm, tn, smem);
+}
+
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
+hipError_t run_jobs(const I8Job *jobs, int njobs, int total, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_fgemm_i8_jobs<S, TM, TN, WGM, WGN, KS, PIPE>), dim3(total),
+                       dim3(64 * WGM * WGN), 0, st, jobs, njobs, total);
+    return hipGetLastError();
+}
+
 template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
 hipError_t run_single(const I8Job &J, hipStream_t st)
 {
@@ -457,6 +488,18 @@ hipError_t launch_i8(int tile, const I8Job &J, hipStream_t st)
     switch (tile) {
 #define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE)                              \
     case id: return run_single<S, TM, TN, WGM, WGN, KS, PIPE>(J, st);
+        FF_I8_TILES(FF_CASE)
+#undef FF_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_i8_jobs(int tile, const I8Job *jobs, int njobs, int total, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    switch (tile) {
+#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE)                              \
+    case id: return run_jobs<S, TM, TN, WGM, WGN, KS, PIPE>(jobs, njobs, total, st);
         FF_I8_TILES(FF_CASE)
 #undef FF_CASE
     default: return hipErrorInvalidValue;

@@ -69,6 +69,8 @@ _SIGS = {
     "ff_ftrsm": ([_U32, _INT, _INT, _INT, _I64, _I64, _U32, _VP, _I64, _VP, _I64], _INT),
     "ff_ftrsm_ex": ([_U32, _INT, _INT, _INT, _I64, _I64, _U32, _VP, _I64, _VP, _I64,
                      ctypes.POINTER(ff_opts)], _INT),
+    "ff_faat": ([_U32, _I64, _I64, _U32, _VP, _I64, _VP, _U32, _VP, _I64,
+                 ctypes.POINTER(ff_opts)], _INT),
     "ff_flqup": ([_U32, _I64, _I64, _VP, _I64, _VP, _VP, _VP, ctypes.POINTER(ff_opts)], _INT),
     "ff_frank": ([_U32, _I64, _I64, _VP, _I64, _VP, ctypes.POINTER(ff_opts)], _INT),
     "ff_fdet": ([_U32, _I64, _VP, _I64, _VP, ctypes.POINTER(ff_opts)], _INT),
@@ -218,6 +220,12 @@ def ff_ftrsm_ex(p, uplo, transT, diag, m, n, alpha, T, ldt, B, ldb, opts=None):
                               o)
 
 
+def ff_faat(p, m, k, alpha, A, lda, D, beta, C, ldc, opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_faat(p, m, k, alpha, _addr(A), lda, _addr(D) if D is not None else None,
+                          beta, _addr(C), ldc, o)
+
+
 def ff_flqup(p, m, n, A, lda, rank, pivrows, colperm, opts=None):
     """rank, pivrows, colperm: numpy int64 arrays (host) of sizes 1, m, n."""
     o = ctypes.byref(opts) if opts is not None else None
@@ -351,6 +359,17 @@ def ftrsm(p, T, B, alpha=1, lower=False, trans=False, unit=False, opts=None):
         opts.stream = _torch_stream()
     return _check(ff_ftrsm_ex(p, int(lower), int(trans), int(unit), m, n, alpha % p, T,
                               _ld(T, 1), B, _ld(B, 1), opts))
+
+
+def aat(p, A, C, D=None, alpha=1, beta=0, opts=None):
+    """C <- alpha A diag(D) A^T + beta C mod p for torch tensors (C m x m,
+    symmetric on return), on torch's current stream."""
+    m, k = A.shape[0], A.shape[1]
+    if opts is None:
+        opts = make_opts()
+    if not opts.stream:
+        opts.stream = _torch_stream()
+    return _check(ff_faat(p, m, k, alpha % p, A, _ld(A, 1), D, beta % p, C, _ld(C, 1), opts))
 
 
 def lqup(p, A, opts=None):
