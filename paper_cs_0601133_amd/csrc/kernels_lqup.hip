@@ -71,7 +71,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
 {
     // published pivot row, column t and search results, double-buffered by
     // row parity so that a row's writes never meet the previous row's reads
-    // (two barriers per row instead of three)
+    // (one barrier per row unless a column exchange is needed)
     __shared__ double s_row[2][PW];
     __shared__ double s_col[2][PR];
     __shared__ double s_swap[2][PR];   // column exchange
@@ -108,12 +108,18 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
     for (int r = 0; r < PR; ++r) {
         if (stuck || r >= nr) continue;
         const int gr = r / PQ, qr = r % PQ, pb = r & 1;
-        // row r: publish it, and find its first nonzero at or after column t
+        // row r: publish it, and find its first nonzero at or after column t;
+        // column t is published at the same time, on the guess (almost always
+        // right) that it holds the pivot, so that one barrier serves both
         if (g == gr) {
             s_row[pb][c] = v[qr];
             const bool nz = c >= t && c < W && v[qr] != 0.0;
             const uint64_t bal = __ballot(nz);
             if (lane == 0) s_first[pb][c / 64] = bal ? (c - lane) + __builtin_ctzll(bal) : PW;
+        }
+        if (c == t) {
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) s_col[pb][r0g + q] = v[q];
         }
         __syncthreads();
         int cmin = PW;
@@ -129,7 +135,8 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
             continue;
         }
         if (cmin != t) {
-            // exchange columns t and cmin in every row of the panel
+            // exchange columns t and cmin in every row of the panel, then
+            // publish the new column t and row r's two changed entries
             if (c == t) {
 #pragma unroll
                 for (int q = 0; q < PQ; ++q) s_swap[0][r0g + q] = v[q];
@@ -142,24 +149,21 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
             if (c == t) {
 #pragma unroll
                 for (int q = 0; q < PQ; ++q) v[q] = s_swap[1][r0g + q];
+#pragma unroll
+                for (int q = 0; q < PQ; ++q) s_col[pb][r0g + q] = v[q];
             }
             if (c == cmin) {
 #pragma unroll
                 for (int q = 0; q < PQ; ++q) v[q] = s_swap[0][r0g + q];
             }
             if (g == gr && (c == t || c == cmin)) s_row[pb][c] = v[qr];
-        }
-        // publish column t (the pivot and the entries below it)
-        if (c == t) {
-#pragma unroll
-            for (int q = 0; q < PQ; ++q) s_col[pb][r0g + q] = v[q];
+            __syncthreads();
         }
         if (tid == 0) {
             s_rowpiv[r] = t;
             s_before[r] = t;
             out[3 + PR + t] = cmin;
         }
-        __syncthreads();
         const double pv = s_col[pb][r];
         if (tid == 0) {
             const double pc = EXACT ? (pv < 0 ? pv + pd : pv) : pv;
