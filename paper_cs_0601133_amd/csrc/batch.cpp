@@ -188,15 +188,16 @@ int upload_batch(BatchPrep &B, char *ws, hipStream_t st, bool sync)
     return FF_OK;
 }
 
-int launch_batch(BatchPrep &B, unsigned *ctr, hipStream_t st, int persistent)
+int launch_batch(BatchPrep &B, unsigned *ctr, hipStream_t st, int persistent, bool slice)
 {
     char *ws = B.bound_ws;
     for (const IJob &j : B.scales)
         FF_HIP_CHECK(launch_scale(j.C, j.ldc, j.m, j.n, j.p, j.beta, st));
     if (B.path == FF_PATH_INT8 && !B.ij.empty()) {
-        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st,
-                              launch_slice_batched((const SliceJob *)(ws + B.off_sj),
-                                                   (int)B.sj.size(), B.slice_blocks, st)));
+        if (slice)
+            FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st,
+                                  launch_slice_batched((const SliceJob *)(ws + B.off_sj),
+                                                       (int)B.sj.size(), B.slice_blocks, st)));
         FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st,
                               launch_i8_batched(B.tile, (const I8Job *)(ws + B.off_ij),
                                                 (int)B.ij.size(), B.i8_tiles, persistent, ctr,

@@ -30,6 +30,56 @@ __host__ __device__ inline int unit_blocks(const SliceJob &J)
 
 typedef uint32_t UnitTile[64][65]; // padded: column reads hit distinct banks
 
+// K-contiguous storage: this thread's share of the 64 x 64 tile of block b
+// (rows r0 + t/16 + 16i, columns 16*kc0 + 4*(t%16) ..), zero outside the
+// operand.  Issues the global loads only.
+__device__ __forceinline__ void load_raw(const SliceJob &J, int b, uint32_t (&w)[4][4])
+{
+    const uint32_t *X = (const uint32_t *)J.X;
+    const int nrb = J.rows_pad / 64;
+    const int r0 = (b % nrb) * 64, kc0 = (b / nrb) * 4;
+    const bool vec = (J.ldx & 3) == 0 && (((uintptr_t)X) & 15) == 0;
+    const int t = threadIdx.x, g = t & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rg = r0 + (t >> 4) + 16 * i, kg = kc0 * 16 + 4 * g;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[i][e] = 0u;
+        if (rg < J.rows) {
+            const uint32_t *src = X + (int64_t)rg * J.ldx + kg;
+            if (vec && kg + 3 < J.K) {
+                const uint4 q = *(const uint4 *)src;
+                w[i][0] = q.x; w[i][1] = q.y; w[i][2] = q.z; w[i][3] = q.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[i][e] = kg + e < J.K ? src[e] : 0u;
+            }
+        }
+    }
+}
+
+// K-contiguous storage: the words of load_raw through the LDS tile to this
+// thread's unit (the whole block must call it).  Returns false if the
+// thread has no unit.
+__device__ __forceinline__ bool unit_from_raw(const SliceJob &J, int b, UnitTile &tile,
+                                              const uint32_t (&w)[4][4], uint32_t *v, int &r,
+                                              int &kc)
+{
+    const int nrb = J.rows_pad / 64;
+    const int r0 = (b % nrb) * 64, kc0 = (b / nrb) * 4;
+    const int t = threadIdx.x, g = t & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tile[(t >> 4) + 16 * i][4 * g + e] = w[i][e];
+    __syncthreads();
+    r = r0 + (t & 63);
+    kc = kc0 + (t >> 6);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = tile[t & 63][(t >> 6) * 16 + e];
+    return kc < J.KP / 16;
+}
+
 // Raw words of this thread's unit in block b (the whole block must call
 // it).  Returns false if the thread has no unit.
 __device__ __forceinline__ bool load_unit(const SliceJob &J, int b, UnitTile &tile,
@@ -52,34 +102,34 @@ __device__ __forceinline__ bool load_unit(const SliceJob &J, int b, UnitTile &ti
         }
         return true;
     }
-    const int nrb = J.rows_pad / 64;
-    const int r0 = (b % nrb) * 64, kc0 = (b / nrb) * 4;
-    const bool vec = (J.ldx & 3) == 0 && (((uintptr_t)X) & 15) == 0;
-    const int g = t & 15;
+    uint32_t w[4][4];
+    load_raw(J, b, w);
+    return unit_from_raw(J, b, tile, w, v, r, kc);
+}
+
+// Writes the S balanced digits of the 16 values of unit (r, kc) into the
+// packed planes at D (layout of the digit slicer: the 16-byte group (r, kc)
+// of digit d at d*plane + (r/RT)*RT*KP + kc*RT*16 + (r%RT)*16).  v is
+// consumed.
+__device__ __forceinline__ void write_digits(const SliceJob &J, int8_t *D, int32_t *v, int r,
+                                             int kc)
+{
+    const int bits = J.S == 1 ? 8 : J.bits;
+    const int sh = 32 - bits;
+    int8_t *dst = D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * 16 +
+                  (int64_t)(r % J.RT) * 16;
+    for (int d = 0; d < J.S; ++d) {
+        uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int rr = (t >> 4) + 16 * i;
-        const int rg = r0 + rr, kg = kc0 * 16 + 4 * g;
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
-        if (rg < J.rows) {
-            const uint32_t *src = X + (int64_t)rg * J.ldx + kg;
-            if (vec && kg + 3 < J.K) {
-                const uint4 q = *(const uint4 *)src;
-                w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) w[e] = kg + e < J.K ? src[e] : 0u;
-            }
+        for (int e = 0; e < 16; ++e) {
+            // balanced digit: the value in [-R/2, R/2) congruent to v mod R,
+            // i.e. the low `bits` bits sign-extended
+            const int dig = (int)((uint32_t)v[e] << sh) >> sh;
+            v[e] = (v[e] - dig) >> bits; // exact division by R
+            w[e >> 2] |= (uint32_t)(dig & 0xFF) << (8 * (e & 3));
         }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) tile[rr][4 * g + e] = w[e];
+        *(uint4 *)(dst + (int64_t)d * J.plane) = make_uint4(w[0], w[1], w[2], w[3]);
     }
-    __syncthreads();
-    r = r0 + (t & 63);
-    kc = kc0 + (t >> 6);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = tile[t & 63][(t >> 6) * 16 + e];
-    return kc < nchunk;
 }
 
 } // namespace ff

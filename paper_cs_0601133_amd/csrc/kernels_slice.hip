@@ -26,20 +26,7 @@ __device__ __forceinline__ void slice_block(const SliceJob &J, int b, UnitTile &
     for (int e = 0; e < 16; ++e)
         v[e] = J.in_mode == IN_SIGNED ? (int32_t)u[e] : center(u[e], J.p, half);
 
-    const int bits = J.S == 1 ? 8 : J.bits;
-    const int Rh = 1 << (bits - 1), mask = (1 << bits) - 1;
-    int8_t *dst = J.D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * 16 +
-                  (int64_t)(r % J.RT) * 16;
-    for (int d = 0; d < J.S; ++d) {
-        uint32_t w[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int dig = ((v[e] + Rh) & mask) - Rh; // balanced digit
-            v[e] = (v[e] - dig) >> bits;                // exact division by R
-            w[e >> 2] |= (uint32_t)(dig & 0xFF) << (8 * (e & 3));
-        }
-        *(uint4 *)(dst + (int64_t)d * J.plane) = make_uint4(w[0], w[1], w[2], w[3]);
-    }
+    write_digits(J, J.D, v, r, kc);
 }
 
 // Both operands of one product in one launch: blocks [0, blocks_a) slice

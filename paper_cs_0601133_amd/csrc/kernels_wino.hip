@@ -1,10 +1,15 @@
 // Winograd pre- and post-additions (Section 3.2, Appendix A), one level per
-// launch.  Both are streaming kernels bound by HBM bandwidth: each thread
+// launch.  All are streaming kernels bound by HBM bandwidth: each thread
 // reads the four quadrant values of one position and writes the seven
 // combinations (pre) or reads seven products and writes four quadrants
-// (post).
+// (post).  On the INT8 path the last level of pre-additions is fused with
+// the digit slicing of the leaves (k_wino_slice), so its seven int32
+// combinations never reach memory.
+#include <algorithm>
+
 #include "ff_device.h"
 #include "ff_internal.h"
+#include "ff_operand.h"
 
 namespace ff {
 
@@ -30,14 +35,14 @@ __device__ __forceinline__ int64_t center_mod(int64_t x, uint32_t p, double pd, 
     return r;
 }
 
-__global__ __launch_bounds__(WT) void k_preadd(PreLevel J)
+// Grid: x covers the columns of one row of quadrant positions, y the rows
+// from i0 on, z the block o of the previous level, so no thread divides.
+__global__ __launch_bounds__(WT) void k_preadd(PreLevel J, int i0)
 {
+    const int j = blockIdx.x * WT + threadIdx.x;
+    if (j >= J.cols) return;
+    const int i = i0 + (int)blockIdx.y, o = blockIdx.z;
     const int64_t per = (int64_t)J.rows * J.cols;
-    const int64_t e = (int64_t)blockIdx.x * WT + threadIdx.x;
-    if (e >= per * J.count_in) return;
-    const int o = (int)(e / per);
-    const int64_t rem = e - (int64_t)o * per;
-    const int i = (int)(rem / J.cols), j = (int)(rem - (int64_t)i * J.cols);
     int64_t v[4];
     const uint32_t half = (J.p - 1) / 2;
 #pragma unroll
@@ -63,14 +68,14 @@ __global__ __launch_bounds__(WT) void k_preadd(PreLevel J)
     }
 }
 
-__global__ __launch_bounds__(WT) void k_postadd(PostLevel J)
+// Same grid as k_preadd.
+__global__ __launch_bounds__(WT) void k_postadd(PostLevel J, int i0)
 {
+    const int j = blockIdx.x * WT + threadIdx.x;
+    if (j >= J.cols) return;
+    const int i = i0 + (int)blockIdx.y, o = blockIdx.z;
     const int64_t per = (int64_t)J.rows * J.cols;
-    const int64_t e = (int64_t)blockIdx.x * WT + threadIdx.x;
-    if (e >= per * J.count_out) return;
-    const int o = (int)(e / per);
-    const int64_t rem = e - (int64_t)o * per;
-    const int i = (int)(rem / J.cols), j = (int)(rem - (int64_t)i * J.cols);
+    const int64_t rem = (int64_t)i * J.cols + j;
     const uint32_t *P = J.P + (int64_t)(o * 7) * per + rem;
     uint64_t x[7];
 #pragma unroll
@@ -83,7 +88,10 @@ __global__ __launch_bounds__(WT) void k_postadd(PostLevel J)
     uint32_t *Y = J.Y + (int64_t)o * J.block_stride;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        uint32_t r = (uint32_t)(q[t] % p);
+        const double qd = (double)q[t]; // < 2^34: exact
+        int64_t rr = (int64_t)__builtin_fma(-__builtin_rint(qd * J.pinv), (double)J.p, qd);
+        rr += rr < 0 ? (int64_t)p : 0;
+        uint32_t r = (uint32_t)rr;
         const int row = (t >> 1) * J.rows + i, col = (t & 1) * J.cols + j;
         uint32_t *yp = Y + (int64_t)row * J.ldy + col;
         if (J.final_level) {
@@ -94,24 +102,170 @@ __global__ __launch_bounds__(WT) void k_postadd(PostLevel J)
     }
 }
 
-unsigned grid_of(int64_t n) { return (unsigned)((n + WT - 1) / WT); }
+// Coefficients of the seven combinations as compile-time constants (the
+// tables above, by side), so that a combination is a few adds.
+template <int SIDE>
+__device__ __forceinline__ constexpr int pre_coef(int t, int q)
+{
+    constexpr int a[7][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {1, 1, -1, -1}, {0, 0, 0, 1},
+                             {0, 0, 1, 1}, {-1, 0, 1, 1}, {1, 0, -1, 0}};
+    constexpr int b[7][4] = {{1, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}, {1, -1, -1, 1},
+                             {-1, 1, 0, 0}, {1, -1, 0, 1}, {0, -1, 0, 1}};
+    return SIDE ? b[t][q] : a[t][q];
+}
+
+// x mod p, centered, for |x| < 2^31 (binary64 quotient estimate; the
+// remainder is exact and at most one step from the range).
+__device__ __forceinline__ int32_t center_mod32(int32_t x, int32_t p, double pd, double pinv)
+{
+    const double xd = (double)x;
+    int32_t r = (int32_t)__builtin_fma(-__builtin_rint(xd * pinv), pd, xd);
+    const int32_t hi = (p - 1) / 2, lo = -(p / 2);
+    r -= r > hi ? p : 0;
+    r += r < lo ? p : 0;
+    return r;
+}
+
+// One unit position of one input block: the four quadrant units are read
+// (all loads issued before the LDS transposes when K-contiguous), the seven
+// combinations formed and sliced into the planes of the block's seven
+// leaves.  NARROW: |values| < 2^29, so four-term sums fit int32.
+template <int SIDE, bool NARROW>
+__device__ __forceinline__ void wino_slice_block(const WinoSlice &W, int b, UnitTile &tile)
+{
+    const int ub = unit_blocks(W.J);
+    const int o = b / ub;
+    b -= o * ub;
+    uint32_t u[4][16];
+    int r = 0, kc = 0;
+    bool ok = false;
+    const uint32_t *base = (const uint32_t *)W.J.X + (int64_t)o * W.block_stride;
+    if (W.J.trans) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            SliceJob J = W.J;
+            J.X = base + W.qoff[q];
+            ok = load_unit(J, b, tile, u[q], r, kc);
+        }
+    } else {
+        uint32_t w[4][4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            SliceJob J = W.J;
+            J.X = base + W.qoff[q];
+            load_raw(J, b, w[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q) __syncthreads(); // every read of the tile by the previous quadrant is done
+            ok = unit_from_raw(W.J, b, tile, w[q], u[q], r, kc);
+        }
+    }
+    if (!ok) return;
+    int32_t c[4][16]; // centered residues or int32 inputs
+    const uint32_t half = (W.J.p - 1) / 2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            c[q][e] = W.J.in_mode == IN_SIGNED ? (int32_t)u[q][e] : center(u[q][e], W.J.p, half);
+    const double pd = (double)W.J.p, pinv = 1.0 / pd;
+    int8_t *D = W.D + (int64_t)o * 7 * W.leaf_stride;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+        int32_t v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            if constexpr (NARROW) {
+                int32_t x = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int cf = pre_coef<SIDE>(t, q);
+                    if (cf > 0) x += c[q][e];
+                    if (cf < 0) x -= c[q][e];
+                }
+                v[e] = W.reduce ? center_mod32(x, (int32_t)W.J.p, pd, pinv) : x;
+            } else {
+                int64_t x = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int cf = pre_coef<SIDE>(t, q);
+                    if (cf > 0) x += c[q][e];
+                    if (cf < 0) x -= c[q][e];
+                }
+                v[e] = (int32_t)(W.reduce ? center_mod(x, W.J.p, pd, pinv) : x);
+            }
+        }
+        write_digits(W.J, D + (int64_t)t * W.leaf_stride, v, r, kc);
+    }
+}
+
+// Both sides in one launch: blocks [0, blocks_a) take a, the rest b.
+template <bool NARROW>
+__global__ __launch_bounds__(UNIT_THREADS) void k_wino_slice(WinoSlice a, WinoSlice b,
+                                                             int blocks_a)
+{
+    __shared__ UnitTile tile;
+    const int blk = blockIdx.x;
+    if (blk < blocks_a)
+        wino_slice_block<0, NARROW>(a, blk, tile);
+    else
+        wino_slice_block<1, NARROW>(b, blk - blocks_a, tile);
+}
+
+// Rows per launch: the y extent of a grid stays within 65535.
+constexpr int ROW_CHUNK = 32768;
+
+dim3 grid_of(int rows, int cols, int count)
+{
+    return dim3((unsigned)((cols + WT - 1) / WT), (unsigned)rows, (unsigned)count);
+}
 
 } // namespace
 
 hipError_t launch_preadd(const PreLevel &J, hipStream_t st)
 {
-    const int64_t n = (int64_t)J.rows * J.cols * J.count_in;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preadd, dim3(grid_of(n)), dim3(WT), 0, st, J);
+    if ((int64_t)J.rows * J.cols * J.count_in == 0) return hipSuccess;
+    if (J.count_in > 65535) return hipErrorInvalidValue;
+    for (int i0 = 0; i0 < J.rows; i0 += ROW_CHUNK) {
+        const int h = std::min(ROW_CHUNK, J.rows - i0);
+        hipLaunchKernelGGL(k_preadd, grid_of(h, J.cols, J.count_in), dim3(WT), 0, st, J, i0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int wino_slice_blocks(const WinoSlice &w) { return w.count * unit_blocks(w.J); }
+
+hipError_t launch_wino_slice(const WinoSlice &a, const WinoSlice &b, hipStream_t st)
+{
+    const int64_t na = (int64_t)a.count * unit_blocks(a.J), nb = (int64_t)b.count * unit_blocks(b.J);
+    if (na + nb == 0) return hipSuccess;
+    if (na + nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    // inputs below 2^29 in magnitude (centered residues of p < 2^30, or the
+    // int32 blocks of a reduced previous level) keep four-term sums in int32
+    const bool narrow = a.J.p < (1u << 30) && (a.J.in_mode == IN_RESIDUE || a.reduce);
+    if (narrow)
+        hipLaunchKernelGGL(k_wino_slice<true>, dim3((unsigned)(na + nb)), dim3(UNIT_THREADS), 0,
+                           st, a, b, (int)na);
+    else
+        hipLaunchKernelGGL(k_wino_slice<false>, dim3((unsigned)(na + nb)), dim3(UNIT_THREADS), 0,
+                           st, a, b, (int)na);
     return hipGetLastError();
 }
 
 hipError_t launch_postadd(const PostLevel &J, hipStream_t st)
 {
-    const int64_t n = (int64_t)J.rows * J.cols * J.count_out;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_postadd, dim3(grid_of(n)), dim3(WT), 0, st, J);
-    return hipGetLastError();
+    if ((int64_t)J.rows * J.cols * J.count_out == 0) return hipSuccess;
+    if (J.count_out > 65535) return hipErrorInvalidValue;
+    for (int i0 = 0; i0 < J.rows; i0 += ROW_CHUNK) {
+        const int h = std::min(ROW_CHUNK, J.rows - i0);
+        hipLaunchKernelGGL(k_postadd, grid_of(h, J.cols, J.count_out), dim3(WT), 0, st, J, i0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 } // namespace ff

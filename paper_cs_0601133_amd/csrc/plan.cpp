@@ -3,7 +3,13 @@
 // * Centered residues (Section 2.1.2: the balanced representation halves
 //   the accumulation bound).  For modulus p they lie in [-(p/2), (p-1)/2].
 // * Winograd levels (Section 3.2.1): l = floor(log2(n/w)) + 1 for the
-//   crossover order w, clamped at 0, or as requested.  Each level's
+//   crossover order w, clamped at 0, or as requested.  The paper leaves w to
+//   experiment; measured here, the order at which the first level pays and
+//   the leaf order at which one more does differ, and both depend on the
+//   leaf arithmetic, so the automatic rule takes a first level at
+//   n >= w_first and each further one while the leaf order stays >= w_next
+//   (w_first = w_next = w is the single-threshold rule; FF_WINOGRAD_W sets
+//   that).  Each level's
 //   pre-additions widen the operand range; with unreduced pre-additions (the
 //   delayed form Theorem 3.1 analyses) the widest leaf operand after l levels
 //   and the largest leaf product term follow from interval arithmetic over
@@ -126,11 +132,27 @@ int choose_i8_tile(int S, int64_t m, int64_t n, int64_t k, const ff_opts &)
     return i8_default_tile(S);
 }
 
-int crossover_w()
+struct Crossover {
+    int64_t first, next;
+};
+
+// Measured on MI355X (square products, one level against none): INT8
+// leaves of one digit never gain (the digit product costs about what the
+// extra passes move); INT8 leaves of 2..5 digits gain 2-13% from n = 3072
+// on with residues below 2^30, and 2% at 12288 above (wider arithmetic in
+// the fused pre-addition); a second INT8 level loses up to 16384.  FP64
+// leaves gain from n = 2048 (the seven leaf products fill the chip where
+// one product at that order does not) and a second level from leaf order
+// 4096.
+Crossover crossover(int path, int s0, uint32_t p)
 {
     const char *e = std::getenv("FF_WINOGRAD_W");
-    if (e && std::atoi(e) > 0) return std::atoi(e);
-    return 16384;
+    if (e && std::atoll(e) > 0) return {std::atoll(e), std::atoll(e)};
+    constexpr int64_t NEVER = int64_t(1) << 62;
+    if (path == FF_PATH_FP64) return {2048, 4096};
+    if (s0 <= 1) return {NEVER, NEVER};
+    if (p >= (1u << 30)) return {12288, 24576};
+    return {3072, 12288};
 }
 
 } // namespace
@@ -177,13 +199,25 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
 
     const Range base{-(int64_t)(p / 2), (int64_t)((p - 1) / 2)};
 
-    // Winograd levels: requested or from the crossover order w.
+    // Winograd levels: requested or from the crossover orders, for the
+    // path this call takes and its digit count without Winograd.
     int L = o.winograd_levels;
     const int64_t dmin = std::min({m, n, k});
+    int path = o.path == FF_PATH_AUTO ? FF_PATH_INT8 : o.path;
     if (L < 0) {
+        int s0 = 0;
+        if (path == FF_PATH_INT8)
+            for (int bits : {7, 8})
+                if (!o.digit_bits || bits == o.digit_bits) {
+                    const int s = slices_for(base, bits);
+                    if (s && (!s0 || s < s0)) s0 = s;
+                }
+        const Crossover w = crossover(path, s0, p);
         L = 0;
-        const int64_t w = crossover_w();
-        for (int64_t x = dmin; x >= w && L < 3; x /= 2) ++L;
+        if (dmin >= w.first) {
+            L = 1;
+            for (int64_t x = dmin / 2; x >= w.next && L < 3; x /= 2) ++L;
+        }
     }
     // Every leaf dimension must keep at least 16 entries.
     while (L > 0 && (dmin >> L) < 16) --L;
@@ -199,7 +233,6 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
     const bool delayed_fits = wid_d.lo >= -I32MAX && wid_d.hi <= I32MAX;
 
     // Path.
-    int path = o.path == FF_PATH_AUTO ? FF_PATH_INT8 : o.path;
     P.path = path;
     const int64_t carry = (int64_t)p + 2;
 
@@ -264,7 +297,15 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         const int64_t mp = round_up(std::max<int64_t>(ml, 1), t.bm());
         const int64_t np = round_up(std::max<int64_t>(nl, 1), t.bn());
         ws += nleaf * P.slices * (mp + np) * KP;
-        if (L > 0) ws += nleaf * ml * nl * 4 + 256;
+        if (L > 0) {
+            // Winograd buffers: int32 combinations of both sides (the last
+            // level's only when not fused into the slicing) and products
+            const int64_t szA = round_up(nleaf * ml * kl * 4, 256),
+                          szB = round_up(nleaf * kl * nl * 4, 256),
+                          szP = round_up(nleaf * ml * nl * 4, 256);
+            const bool fused = kpass == kl && wino_fused_enabled();
+            ws += (fused ? 0 : szA + szB) + (L > 1 ? szA + szB + szP : 0) + szP;
+        }
     } else {
         // packed double operands of every leaf
         const F64Tile &t = f64_tile(P.tile);

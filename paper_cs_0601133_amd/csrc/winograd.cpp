@@ -22,7 +22,13 @@
 // top-left block goes through Winograd, the leftover strips are thin
 // products added afterwards (the dynamic peeling of Appendix A, done once
 // for all levels).
+//
+// On the INT8 path with the leaf K in one int32 pass, the last level of
+// pre-additions is fused with the digit slicing of the leaves: the seven
+// combinations of each quadrant quadruple are sliced in registers straight
+// into the leaves' packed planes (FF_WINO_FUSED=0 runs them apart).
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -30,6 +36,12 @@
 #include "ff_profile.h"
 
 namespace ff {
+
+bool wino_fused_enabled()
+{
+    const char *e = std::getenv("FF_WINO_FUSED");
+    return !(e && *e == '0');
+}
 
 namespace {
 
@@ -48,6 +60,64 @@ const uint32_t *sub(const uint32_t *X, int64_t ld, int trans, int64_t r0, int64_
     return trans ? X + c0 * ld + r0 : X + r0 * ld + c0;
 }
 
+// Descriptors of the fused last level, both sides, from the leaf batch's
+// own slicing layout (leaf q: A planes in sj[2q], B^T planes in sj[2q+1]).
+// The last level reads the residues of op(A), op(B) when L == 1, else the
+// int32 blocks of level L-1: A blocks 2ml x 2kl, B blocks 2kl x 2nl, both
+// row-major.
+int fused_slices(const BatchPrep &bp, char *ws, int L, int transA, int transB, int64_t ml,
+                 int64_t nl, int64_t kl, const uint32_t *A, int64_t lda, const uint32_t *B,
+                 int64_t ldb, const void *const lastIn[2], int reduce, WinoSlice w[2])
+{
+    const int64_t nleaf = pow7(L);
+    if ((int64_t)bp.sj.size() != 2 * nleaf || (int64_t)bp.ij.size() != nleaf)
+        return fail(FF_EUNSUPPORTED, "fused Winograd slicing: unexpected leaf batch");
+    const intptr_t a0 = (intptr_t)bp.sj[0].D, b0 = (intptr_t)bp.sj[1].D;
+    const intptr_t stride = nleaf > 1 ? (intptr_t)bp.sj[2].D - a0 : 0;
+    for (int64_t q = 0; q < nleaf; ++q)
+        if ((intptr_t)bp.sj[2 * q].D != a0 + q * stride ||
+            (intptr_t)bp.sj[2 * q + 1].D != b0 + q * stride)
+            return fail(FF_EUNSUPPORTED, "fused Winograd slicing: leaf planes not evenly spaced");
+    char *planes = ws + bp.off_planes;
+    for (int side = 0; side < 2; ++side) {
+        WinoSlice &W = w[side];
+        std::memset(&W, 0, sizeof(W));
+        W.J = bp.sj[side];
+        W.side = side;
+        W.reduce = reduce;
+        W.D = (int8_t *)(planes + (side ? b0 : a0));
+        W.leaf_stride = (int64_t)stride;
+        W.count = (int)(nleaf / 7);
+        for (int q = 0; q < 4; ++q) {
+            const int64_t qr = q >> 1, qc = q & 1;
+            if (L == 1) {
+                W.J.in_mode = IN_RESIDUE;
+                if (side == 0) { // quadrant (qr, qc) of op(A), m x k
+                    W.J.X = A; W.J.ldx = lda; W.J.trans = transA;
+                    W.qoff[q] = transA ? qc * kl * lda + qr * ml : qr * ml * lda + qc * kl;
+                } else { // quadrant (qr, qc) of op(B), k x n, read as B^T
+                    W.J.X = B; W.J.ldx = ldb; W.J.trans = transB ? 0 : 1;
+                    W.qoff[q] = transB ? qc * nl * ldb + qr * kl : qr * kl * ldb + qc * nl;
+                }
+                W.block_stride = 0;
+            } else {
+                W.J.in_mode = IN_SIGNED;
+                W.J.X = lastIn[side];
+                if (side == 0) {
+                    W.J.ldx = 2 * kl; W.J.trans = 0;
+                    W.qoff[q] = qr * ml * 2 * kl + qc * kl;
+                    W.block_stride = 4 * ml * kl;
+                } else {
+                    W.J.ldx = 2 * nl; W.J.trans = 1;
+                    W.qoff[q] = qr * kl * 2 * nl + qc * nl;
+                    W.block_stride = 4 * kl * nl;
+                }
+            }
+        }
+    }
+    return FF_OK;
+}
+
 } // namespace
 
 int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
@@ -64,13 +134,15 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
     // passes when an int32 pass cannot hold the whole leaf K (INT8 path).
     const int64_t kpass = P.path == FF_PATH_INT8 ? std::min<int64_t>(kl, P.kblock) : kl;
     const int npass = (int)((kl + kpass - 1) / kpass);
+    const bool fused = P.path == FF_PATH_INT8 && npass == 1 && wino_fused_enabled();
 
-    // workspace layout
+    // workspace layout (fused: the last level's combinations, which would
+    // land in buffer 0, are never stored)
     const int64_t szA = nleaf * ml * kl * 4, szB = nleaf * kl * nl * 4, szP = nleaf * ml * nl * 4;
     int64_t off = 0;
-    const int64_t oA0 = off; off = align256(off + szA);
+    const int64_t oA0 = off; off = align256(off + (fused ? 0 : szA));
     const int64_t oA1 = off; off = align256(off + (L > 1 ? szA : 0));
-    const int64_t oB0 = off; off = align256(off + szB);
+    const int64_t oB0 = off; off = align256(off + (fused ? 0 : szB));
     const int64_t oB1 = off; off = align256(off + (L > 1 ? szB : 0));
     const int64_t oP0 = off; off = align256(off + szP);
     const int64_t oP1 = off; off = align256(off + (L > 1 ? szP : 0));
@@ -96,10 +168,13 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
     unsigned *ctr = nullptr;
     if ((rc = counter_buffer(st, &ctr))) return rc;
 
-    // Pre-additions, level by level, for both sides.
+    // Pre-additions, level by level, for both sides (fused: all but the
+    // last level; src is then the last level's input).
     int32_t *Abuf[2] = {(int32_t *)(ws + oA0), (int32_t *)(ws + oA1)};
     int32_t *Bbuf[2] = {(int32_t *)(ws + oB0), (int32_t *)(ws + oB1)};
     const int32_t *leafA = nullptr, *leafB = nullptr;
+    const void *lastIn[2] = {nullptr, nullptr};
+    const int Lpre = fused ? L - 1 : L;
     for (int side = 0; side < 2; ++side) {
         const void *src = side ? (const void *)B : (const void *)A;
         int64_t ld = side ? ldb : lda;
@@ -107,7 +182,7 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
         int64_t rows = side ? ke : me, cols = side ? ne : ke;
         int64_t count = 1;
         int32_t **buf = side ? Bbuf : Abuf;
-        for (int l = 1; l <= L; ++l) {
+        for (int l = 1; l <= Lpre; ++l) {
             PreLevel J;
             std::memset(&J, 0, sizeof(J));
             J.X = src; J.ldx = ld; J.trans = l == 1 ? tr : 0; J.in_residue = l == 1;
@@ -125,6 +200,7 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
             count *= 7;
         }
         (side ? leafB : leafA) = (const int32_t *)src;
+        lastIn[side] = src;
     }
 
     // Leaf products into P0 (reduced residues, alpha = 1, beta = 0).
@@ -137,8 +213,9 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
         const int64_t kc = std::min<int64_t>(kpass, kl - k0);
         std::vector<IJob> js = leaves;
         for (int64_t q = 0; q < nleaf; ++q) {
-            js[q].A = leafA + q * ml * kl + k0;
-            js[q].B = leafB + q * kl * nl + k0 * nl;
+            // fused: the leaves' operands exist only as digit planes
+            js[q].A = fused ? nullptr : leafA + q * ml * kl + k0;
+            js[q].B = fused ? nullptr : leafB + q * kl * nl + k0 * nl;
             js[q].C = leafP + q * ml * nl;
             js[q].k = kc;
             js[q].beta = pass == 0 ? 0u : 1u;
@@ -146,7 +223,14 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
         BatchPrep bp;
         if ((rc = prep_batch(js, P.path, P.tile, &bp))) return rc;
         if ((rc = upload_batch(bp, ws + oBatch, st, false))) return rc;
-        if ((rc = launch_batch(bp, ctr, st, 0))) return rc;
+        if (fused) {
+            WinoSlice w[2];
+            if ((rc = fused_slices(bp, ws + oBatch, L, transA, transB, ml, nl, kl, A, lda, B, ldb,
+                                   lastIn, P.preadds_reduced, w)))
+                return rc;
+            FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_wino_slice(w[0], w[1], st)));
+        }
+        if ((rc = launch_batch(bp, ctr, st, 0, !fused))) return rc;
     }
 
     // Post-additions, level by level up to C.

@@ -138,6 +138,42 @@ def test_plan_fp64_tiles_and_split_k_workspace():
     assert i.workspace_bytes == (128 + 128) * stages * 16 * 8 + 256 + splits * 3 * 5 * 4
 
 
+def test_plan_automatic_winograd_levels(monkeypatch):
+    # Section 3.2.1 leaves the crossover to experiment.  Automatic levels:
+    # a first level at min(m, n, k) >= w_first, one more per halving while
+    # the leaf order stays >= w_next.  INT8 with one digit: never; INT8 with
+    # more digits: (3072, 12288) below p = 2^30, (12288, 24576) above;
+    # FP64: (2048, 4096).  FF_WINOGRAD_W = w is the paper's
+    # l = floor(log2(n / w)) + 1.
+    monkeypatch.delenv("FF_WINOGRAD_W", raising=False)
+    i8, f64 = ff.make_opts(path=ff.FF_PATH_INT8), ff.make_opts(path=ff.FF_PATH_FP64)
+
+    def lv(p, n, o, m=None, k=None):
+        return ff.ff_plan_query(p, 0, 0, m or n, n, k or n, o).winograd_levels
+
+    assert lv(251, 32768, i8) == 0
+    assert [lv(8388593, n, i8) for n in (3071, 3072, 24575, 24576)] == [0, 1, 1, 2]
+    assert lv(8388593, 8192, i8, k=2048) == 0            # the smallest order decides
+    assert [lv(2147483647, n, i8) for n in (12287, 12288, 49152)] == [0, 1, 2]
+    assert [lv(65521, n, f64) for n in (2047, 2048, 8191, 8192, 16384)] == [0, 1, 1, 2, 3]
+    monkeypatch.setenv("FF_WINOGRAD_W", "5000")
+    assert [lv(8388593, n, i8) for n in (4999, 5000, 10000, 20000)] == [0, 1, 2, 3]
+    assert lv(251, 5000, i8) == 1
+
+
+def test_plan_int8_winograd_workspace(monkeypatch):
+    # INT8 leaves in one int32 pass: the last level's seven int32
+    # combinations per side are sliced in registers, so the workspace holds
+    # no buffer for them (m = n = k = 4096, one level: 7 leaves of 2048^2
+    # int32 per side)
+    o = ff.make_opts(path=ff.FF_PATH_INT8, winograd_levels=1)
+    monkeypatch.delenv("FF_WINO_FUSED", raising=False)
+    fused = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096, o).workspace_bytes
+    monkeypatch.setenv("FF_WINO_FUSED", "0")
+    apart = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096, o).workspace_bytes
+    assert apart - fused == 2 * 7 * 2048 * 2048 * 4
+
+
 @pytest.mark.parametrize("args,msg", [
     ((1, 0, 0, 4, 4, 4, 1, 8, 4, 8, 4, 0, 8, 4), "p must"),
     ((7, 2, 0, 4, 4, 4, 1, 8, 4, 8, 4, 0, 8, 4), "trans"),

@@ -2,7 +2,9 @@
 
 Covers 1 and 2 levels, delayed (unreduced) and reduced pre-additions,
 dimensions that are not multiples of 2^l (peeling), alpha/beta and
-transposes, and the 8192^3 product at p = 8388593 (sampled + Freivalds).
+transposes, the INT8 path with its last pre-addition level fused into the
+digit slicing (the default) and kept apart (FF_WINO_FUSED=0), and the
+8192^3 product at p = 8388593 (sampled + Freivalds).
 """
 import numpy as np
 import pytest
@@ -20,10 +22,13 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("path,bits", [(ff.FF_PATH_INT8, 7), (ff.FF_PATH_INT8, 8),
-                                       (ff.FF_PATH_FP64, 0)], ids=["int8d7", "int8d8", "fp64"])
+@pytest.mark.parametrize("path,bits,fused", [(ff.FF_PATH_INT8, 7, "1"), (ff.FF_PATH_INT8, 8, "1"),
+                                             (ff.FF_PATH_INT8, 7, "0"), (ff.FF_PATH_INT8, 8, "0"),
+                                             (ff.FF_PATH_FP64, 0, "1")],
+                         ids=["int8d7", "int8d8", "int8d7_apart", "int8d8_apart", "fp64"])
 @pytest.mark.parametrize("mode", [1, 2], ids=["delayed", "reduced"])
-def test_winograd_levels(path, bits, mode):
+def test_winograd_levels(path, bits, fused, mode, monkeypatch):
+    monkeypatch.setenv("FF_WINO_FUSED", fused)
     for ci, (p, m, n, k, L) in enumerate(CASES):
         tA, tB = bool(ci & 1), bool(ci & 2)
         A = synth.residues(synth.seed_for(60 + ci, 1), (k, m) if tA else (m, k), p)
@@ -43,8 +48,8 @@ def test_winograd_levels(path, bits, mode):
 
 
 @pytest.mark.parametrize("L", [1, 2])
-@pytest.mark.parametrize("path,bits", [(ff.FF_PATH_INT8, 7), (ff.FF_PATH_FP64, 0)],
-                         ids=["int8d7", "fp64"])
+@pytest.mark.parametrize("path,bits", [(ff.FF_PATH_INT8, 7), (ff.FF_PATH_INT8, 8),
+                                       (ff.FF_PATH_FP64, 0)], ids=["int8d7", "int8d8", "fp64"])
 def test_winograd_full_size_8192(L, path, bits):
     p = 8388593
     A = synth.residues(synth.seed_for(3, 1), (8192, 8192), p)
