@@ -475,6 +475,18 @@ int ff_fgemm_ex(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_
     if (P.levels > 0)
         return run_winograd(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                             P, o, st);
+    if (P.path == FF_PATH_FP64 && P.small) {
+        F64Small J;
+        std::memset(&J, 0, sizeof(J));
+        J.A = A; J.B = B; J.lda = lda; J.ldb = ldb; J.ta = transA; J.tb = transB;
+        J.C = C; J.ldc = ldc;
+        J.m = (int)m; J.n = (int)n; J.k = (int)k;
+        J.p = p; J.alpha = alpha; J.beta = beta;
+        J.pd = (double)p; J.pinv = 1.0 / (double)p;
+        J.fold_steps = (int)std::min<int64_t>(P.kblock / 4, 0x3FFFFFFF);
+        FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_f64_small(J, st)));
+        return FF_OK;
+    }
     void *ws = nullptr;
     if ((rc = workspace(st, (size_t)P.ws_bytes, &ws))) return rc;
     if (P.path == FF_PATH_FP64)

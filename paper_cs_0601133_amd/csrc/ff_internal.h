@@ -88,6 +88,7 @@ struct Plan {
     int64_t max_prod = 0;    // bound on |a*b| of one leaf product term
     int64_t kblock = 0;      // FP64: products between folds; INT8: K per pass
     int tile = 0;
+    int small = 0;           // FP64 without Winograd in one launch (no workspace)
     int64_t ws_bytes = 0;
     // leaf problem shape (after peeling the top level to multiples of 2^L)
     int64_t me = 0, ne = 0, ke = 0;
@@ -136,6 +137,25 @@ struct F64Job {
     int kt_split;
     uint32_t *part;
 };
+
+// Small FP64 product in one launch (kernels_small.hip): C <- alpha op(A)
+// op(B) + beta C (mod p) read straight from the residues, reduced every
+// fold_steps 4-product steps.
+struct F64Small {
+    const uint32_t *A, *B;
+    int64_t lda, ldb;
+    int ta, tb;
+    uint32_t *C;
+    int64_t ldc;
+    int m, n, k;
+    uint32_t p, alpha, beta;
+    double pd, pinv;
+    int fold_steps;
+};
+hipError_t launch_f64_small(const F64Small &J, hipStream_t st);
+// Whether an FP64 product without Winograd takes the one-launch kernel
+// (FF_F64_SMALL=0 never, =1 always, else by size).
+bool f64_small(int64_t m, int64_t n, int64_t k);
 
 // Slicing task: one operand of one job into packed digit planes.
 struct SliceJob {

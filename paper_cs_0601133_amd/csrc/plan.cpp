@@ -157,6 +157,17 @@ Crossover crossover(int path, int s0, uint32_t p)
 
 } // namespace
 
+// Products small enough that the three launches of the general FP64 path
+// (packing, GEMM with a K split, split reduction) cost more than one
+// launch of 32 x 32 tiles over the whole K.
+bool f64_small(int64_t m, int64_t n, int64_t k)
+{
+    const char *e = std::getenv("FF_F64_SMALL");
+    if (e && *e == '0') return false;
+    if (e && *e == '1') return true;
+    return m * n <= 512 * 512 && k <= 768;
+}
+
 // FF_F64_TILE (an id) overrides the default FP64 configuration; products
 // of at most 1024 x 1024 take the 128 x 128 tile (more workgroups).
 int choose_f64_tile(int64_t m, int64_t n)
@@ -315,6 +326,9 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         ws += nleaf * (mp + np) * KP * 8;
         if (L > 0) {
             ws += nleaf * (ml * kl + kl * nl) * 4 + nleaf * ml * nl * 4 + 256;
+        } else if (f64_small(m, n, k)) {
+            P.small = 1;
+            ws = 0; // residues are read in place
         } else {
             int kts = 0;
             const int ns = f64_splits((mp / t.bm()) * (np / t.bn()), KP / F64_BK, &kts);

@@ -164,11 +164,12 @@ def _addr(x):
 def _ld(x, default):
     if x is None or isinstance(x, int):
         return default
-    if x.dim() != 2:
+    sh, st = x.shape, x.stride()
+    if len(sh) != 2:
         raise ValueError("matrices must be 2-D")
-    if x.shape[1] > 1 and x.stride(1) != 1:
+    if sh[1] > 1 and st[1] != 1:
         raise ValueError("matrices must have unit column stride (row-major)")
-    return max(x.stride(0), x.shape[1], 1)
+    return max(st[0], sh[1], 1)
 
 
 def make_opts(path=FF_PATH_AUTO, winograd_levels=-1, digit_bits=0, validate=0,
@@ -403,10 +404,15 @@ def det(p, A, opts=None):
 
 def fgemm(p, A, B, C, alpha=1, beta=0, transA=False, transB=False, opts=None):
     """C <- (alpha*op(A)*op(B) + beta*C) mod p on torch's current stream."""
-    j = job(p, A, B, C, alpha, beta, transA, transB)
+    m = A.shape[1] if transA else A.shape[0]
+    k = A.shape[0] if transA else A.shape[1]
+    n = B.shape[0] if transB else B.shape[1]
     if opts is None:
         opts = make_opts()
     if not opts.stream:
         opts.stream = _torch_stream()
-    return _check(ff_fgemm_ex(j.p, j.transA, j.transB, j.m, j.n, j.k, j.alpha, j.A, j.lda,
-                              j.B, j.ldb, j.beta, j.C, j.ldc, opts))
+    # straight to the C entry point (small products are latency-bound)
+    rc = load().ff_fgemm_ex(p, int(transA), int(transB), m, n, k, alpha % p, _addr(A),
+                            _ld(A, 1), _addr(B), _ld(B, 1), beta % p, _addr(C), _ld(C, 1),
+                            ctypes.byref(opts))
+    return rc if rc == FF_OK else _check(rc)

@@ -116,12 +116,24 @@ def test_plan_configs_of_the_workloads():
         assert i.kblock == kb
 
 
-def test_plan_fp64_tiles_and_split_k_workspace():
+def test_plan_fp64_small_products_need_no_workspace(monkeypatch):
+    # m * n <= 512^2 and k <= 768: one launch reads the residues in place
+    monkeypatch.delenv("FF_F64_SMALL", raising=False)
+    o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0)
+    assert ff.ff_plan_query(65521, 0, 0, 256, 256, 256, o).workspace_bytes == 0
+    assert ff.ff_plan_query(65521, 0, 0, 512, 512, 768, o).workspace_bytes == 0
+    assert ff.ff_plan_query(65521, 0, 0, 512, 512, 769, o).workspace_bytes > 0
+    assert ff.ff_plan_query(65521, 0, 0, 513, 512, 64, o).workspace_bytes > 0
+
+
+def test_plan_fp64_tiles_and_split_k_workspace(monkeypatch):
     # FP64 products up to 1024 x 1024 take the 128 x 128 tile (id 2), larger
     # ones the 256 x 128 tile (id 1).  A single launch with fewer than 128
     # tiles splits K into min(K stages, 512 / tiles) parts; the workspace is
     # the packed operands (8 bytes per padded element) plus, 256-aligned,
-    # one uint32 partial product per split.
+    # one uint32 partial product per split.  (Small products take the
+    # one-launch kernel by default; FF_F64_SMALL=0 keeps the general path.)
+    monkeypatch.setenv("FF_F64_SMALL", "0")
     o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0)
     i = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096, o)
     assert i.tile_config == 1

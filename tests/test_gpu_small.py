@@ -1,0 +1,62 @@
+"""The one-launch FP64 kernel for small products, bit-exact vs the oracle.
+
+The kernel reads the residues in place (all four transpose combinations),
+centers them on the way into LDS, delays the reduction by the plan's
+K-block (folds every 2 steps at p = 2^26 - 5, never at p = 65521 for these
+depths) and applies alpha and beta in the epilogue.  Ragged shapes cover
+partial 32 x 32 tiles and partial 64-deep K stages.  The general FP64 path
+(packing, K split, split reduction) is checked on the same shapes with
+FF_F64_SMALL=0, and both paths must agree.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import from_dev, to_dev
+from paper_cs_0601133_amd import ffgemm as ff
+from paper_cs_0601133_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1, 1), (31, 33, 65), (32, 32, 64), (256, 256, 256), (300, 200, 2048),
+          (5, 700, 130), (512, 512, 67)]
+PRIMES = [2, 3, 251, 65521, 8388593, 67108859]
+
+
+def run(p, A, B, C, alpha, beta, tA, tB):
+    dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+    ff.fgemm(p, dA, dB, dC, alpha, beta, tA, tB,
+             ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0))
+    return from_dev(dC)
+
+
+@pytest.mark.parametrize("mode", ["1", "0"], ids=["one_launch", "general"])
+def test_small_fp64_products(mode, monkeypatch):
+    monkeypatch.setenv("FF_F64_SMALL", mode)
+    for si, (m, n, k) in enumerate(SHAPES):
+        for pi, p in enumerate(PRIMES):
+            tA, tB = bool((si + pi) & 1), bool((si + pi) & 2)
+            seed = 900 + 10 * si + pi
+            A = synth.residues(synth.seed_for(seed, 1), (k, m) if tA else (m, k), p)
+            B = synth.residues(synth.seed_for(seed, 2), (n, k) if tB else (k, n), p)
+            C = synth.residues(synth.seed_for(seed, 3), (m, n), p)
+            alpha, beta = (p - 1) % p, 3 % p
+            got = run(p, A, B, C, alpha, beta, tA, tB)
+            want = oracle.fgemm(p, A, B, C, alpha, beta, tA, tB)
+            assert np.array_equal(got, want), (mode, m, n, k, p, tA, tB)
+
+
+def test_small_fp64_beta_zero_and_extreme_residues(monkeypatch):
+    # all entries p - 1 (centered -1) and (p - 1) / 2 (the largest centered
+    # value): the K-block bound is met with equality patterns; beta = 0
+    # must not read C (filled with values >= p here)
+    monkeypatch.setenv("FF_F64_SMALL", "1")
+    for p in (8388593, 67108859):
+        for fill in (p - 1, (p - 1) // 2):
+            m, n, k = 64, 96, 2048
+            A = np.full((m, k), fill, np.uint32)
+            B = np.full((k, n), fill, np.uint32)
+            C = np.full((m, n), 0xFFFFFFFF, np.uint32)
+            got = run(p, A, B, C, 1, 0, False, False)
+            want = oracle.fgemm(p, A, B, np.zeros((m, n), np.uint32), 1, 0, False, False)
+            assert np.array_equal(got, want), (p, fill)

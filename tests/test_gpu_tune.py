@@ -47,8 +47,11 @@ def test_autotune_rejects_bad_arguments():
 
 
 @pytest.mark.parametrize("path", [ff.FF_PATH_INT8, ff.FF_PATH_FP64], ids=["int8", "fp64"])
-def test_profile_mask_selects_kernels(path):
+def test_profile_mask_selects_kernels(path, monkeypatch):
     import torch
+    # the general FP64 path (packing launch + GEMM launch), not the one-launch
+    # kernel this size would otherwise take
+    monkeypatch.setenv("FF_F64_SMALL", "0")
     p = 65521
     A = synth.residues(synth.seed_for(71, 1), (300, 200), p)
     B = synth.residues(synth.seed_for(71, 2), (200, 260), p)
@@ -71,4 +74,24 @@ def test_profile_mask_selects_kernels(path):
     assert g["gemm_launches"] == 1 and g["slice_launches"] == 0 and g["gemm_ms"] > 0
     assert s["gemm_launches"] == 0 and s["slice_launches"] == 1 and s["slice_ms"] > 0
     assert z["gemm_launches"] == 0 and z["slice_launches"] == 0
+    assert np.array_equal(from_dev(dC), oracle.fgemm(p, A, B))
+
+
+def test_profile_one_launch_fp64_small_product(monkeypatch):
+    import torch
+    monkeypatch.delenv("FF_F64_SMALL", raising=False)
+    p = 65521
+    A = synth.residues(synth.seed_for(72, 1), (300, 200), p)
+    B = synth.residues(synth.seed_for(72, 2), (200, 260), p)
+    dA, dB = to_dev(A), to_dev(B)
+    dC = to_dev(np.zeros((300, 260), np.uint32))
+    o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0)
+    try:
+        ff.ff_profile_enable(ff.FF_PROFILE_GEMM | ff.FF_PROFILE_PREP)
+        ff.fgemm(p, dA, dB, dC, opts=o)
+        g = ff.ff_profile_read()
+    finally:
+        ff.ff_profile_enable(0)
+    torch.cuda.synchronize()
+    assert g["gemm_launches"] == 1 and g["slice_launches"] == 0
     assert np.array_equal(from_dev(dC), oracle.fgemm(p, A, B))
