@@ -409,6 +409,25 @@ int validate_inputs(uint32_t p, int transA, int transB, int64_t m, int64_t n, in
 // ---------------------------------------------------------------------------
 using namespace ff;
 
+namespace ff {
+
+// Plan of one ff_fgemm_ex call.  The automatic path takes FP64 for a
+// product small enough for the one-launch kernel (a single launch where the
+// INT8 path slices and then multiplies), when no digit width is asked for
+// and the FP64 K-block allows the modulus; otherwise the planner's choice.
+static int plan_call(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o, Plan *P)
+{
+    if (o.path == FF_PATH_AUTO && o.digit_bits == 0 && o.winograd_levels <= 0 &&
+        f64_small(m, n, k)) {
+        ff_opts fo = o;
+        fo.path = FF_PATH_FP64;
+        if (make_plan(p, m, n, k, fo, P) == FF_OK && P->small) return FF_OK;
+    }
+    return make_plan(p, m, n, k, o, P);
+}
+
+} // namespace ff
+
 extern "C" {
 
 int ff_init(void) { return check_device(); }
@@ -432,7 +451,7 @@ int ff_plan_query(uint32_t p, int transA, int transB, int64_t m, int64_t n, int6
     if (m < 0 || n < 0 || k < 0) return fail(FF_EINVAL, "negative dimension");
     ff_opts o = opts ? *opts : default_opts();
     Plan P;
-    int rc = make_plan(p, m, n, k, o, &P);
+    int rc = plan_call(p, m, n, k, o, &P);
     if (rc) return rc;
     std::memset(out, 0, sizeof(*out));
     out->path = P.path;
@@ -471,7 +490,7 @@ int ff_fgemm_ex(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_
         return FF_OK;
     }
     Plan P;
-    if ((rc = make_plan(p, m, n, k, o, &P))) return rc;
+    if ((rc = plan_call(p, m, n, k, o, &P))) return rc;
     if (P.levels > 0)
         return run_winograd(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                             P, o, st);

@@ -126,6 +126,23 @@ def test_plan_fp64_small_products_need_no_workspace(monkeypatch):
     assert ff.ff_plan_query(65521, 0, 0, 513, 512, 64, o).workspace_bytes > 0
 
 
+def test_plan_automatic_path_for_small_products(monkeypatch):
+    # the automatic path takes the one-launch FP64 kernel for small products
+    # where the FP64 K-block allows the modulus and no digit width is asked
+    # for; INT8 otherwise
+    monkeypatch.delenv("FF_F64_SMALL", raising=False)
+
+    def path(p, m, n, k, **kw):
+        return ff.ff_plan_query(p, 0, 0, m, n, k, ff.make_opts(**kw)).path
+
+    assert path(65521, 256, 256, 256) == ff.FF_PATH_FP64
+    assert path(251, 64, 512, 768) == ff.FF_PATH_FP64
+    assert path(65521, 256, 256, 256, digit_bits=7) == ff.FF_PATH_INT8
+    assert path(2147483647, 256, 256, 256) == ff.FF_PATH_INT8   # FP64 K-block < 4
+    assert path(65521, 1024, 1024, 1024) == ff.FF_PATH_INT8
+    assert path(65521, 256, 256, 769) == ff.FF_PATH_INT8
+
+
 def test_plan_fp64_tiles_and_split_k_workspace(monkeypatch):
     # FP64 products up to 1024 x 1024 take the 128 x 128 tile (id 2), larger
     # ones the 256 x 128 tile (id 1).  A single launch with fewer than 128
