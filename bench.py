@@ -62,6 +62,10 @@ def parse():
                     help="time only the symmetric product (profiler runs)")
     ap.add_argument("--lqup-only", action="store_true",
                     help="time only the LQUP factorisations (profiler runs)")
+    ap.add_argument("--n8192-only", action="store_true",
+                    help="time only the 8192^3 products with 0-2 Winograd levels (profiler runs)")
+    ap.add_argument("--latency-only", action="store_true",
+                    help="time only the 256^3 latency workload (profiler runs)")
     return ap.parse_args()
 
 
@@ -446,6 +450,12 @@ def main():
         return
     if args.lqup_only:
         print(json.dumps({"workloads": {"lqup": factorisation(torch, ff, args)}}))
+        return
+    if args.n8192_only:
+        print(json.dumps({"workloads": {"n8192": large_8192(torch, ff, args)}}))
+        return
+    if args.latency_only:
+        print(json.dumps({"workloads": {"n256_p65521_latency": small_latency(torch, ff, args)}}))
         return
     paths, (A, B, C) = headline(torch, ff, args)
     head = paths["int8_d7"]

@@ -60,3 +60,21 @@ def test_winograd_full_size_8192(L, path, bits):
                                                     winograd_levels=L))
     err = check_sampled(p, A, B, C, from_dev(dC), 1, 0, count=256, seed=L, trials=2)
     assert err is None, err
+
+
+def test_winograd_rows_beyond_one_launch():
+    # FP64 leaves with one level at m = 65540: the pre- and post-addition
+    # kernels cover the 32770 quadrant rows in two launches of at most
+    # 32768 rows each (the grid's y extent); an odd trailing row pair and
+    # a peeled last row are covered too (65541 rows)
+    for m in (65540, 65541):
+        p, n, k = 65521, 64, 64
+        A = synth.residues(synth.seed_for(80, 1), (m, k), p)
+        B = synth.residues(synth.seed_for(80, 2), (k, n), p)
+        C = synth.residues(synth.seed_for(80, 3), (m, n), p)
+        o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=1)
+        assert ff.ff_plan_query(p, 0, 0, m, n, k, o).winograd_levels == 1
+        dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+        ff.fgemm(p, dA, dB, dC, 2, 7, opts=o)
+        want = oracle.fgemm(p, A, B, C, 2, 7)
+        assert np.array_equal(from_dev(dC), want), m
