@@ -248,6 +248,12 @@ hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uin
 // (64 x 64 row-major each); split as for the leaf.
 hipError_t launch_trsm_inv(const uint32_t *Tn, int64_t ldn, int lower, uint32_t p, int split,
                            uint32_t *Tinv, hipStream_t st);
+// The same for a system of m <= 64 rows, read straight from op(T) (trans:
+// op(T) = T^T) and scaled by dinv (null: unit), with no Tn: its single
+// leaf needs only the inverse.
+hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int lower,
+                                  int64_t m, uint32_t p, int split, const uint32_t *dinv,
+                                  uint32_t *Tinv, hipStream_t st);
 // Solves rows [r0, r0 + rows) of Tn X = B in place, every other row's
 // contribution already subtracted; r0 a multiple of 64, rows <=
 // TRSM_LEAF_MAX.  split: operands cut in two (needed once

@@ -136,9 +136,21 @@ __device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 // in binary64 under the bound of the leaf solve (SPLIT: the entries of T'
 // cut in two as there).  Row l, reduced, reaches the lanes of its column by
 // a shuffle: no barrier inside the 64 steps.
-template <bool SPLIT, bool LOWER>
+//
+// DIRECT (systems of at most 64 rows, whose one leaf reads no T'): the
+// entries come straight from op(T) (InvDirect), restricted to the triangle
+// and scaled by the diagonal inverses here, so T' is never formed.
+struct InvDirect {
+    const uint32_t *T;
+    int64_t ldt;
+    int trans;
+    int m;
+    const uint32_t *dinv; // null: unit diagonal
+};
+
+template <bool SPLIT, bool LOWER, bool DIRECT>
 __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn, uint32_t p,
-                                                 double pinv, uint32_t *Tinv)
+                                                 double pinv, uint32_t *Tinv, InvDirect d)
 {
     // sT[.][l][i] = T'(i, l), diagonal 0; rows padded to 65 so that the
     // transposing stores (one l per lane) spread over the banks
@@ -148,13 +160,32 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
     const int j = 16 * jq + jl;
     const uint32_t half = (p - 1) / 2;
     const double pd = (double)p;
-    const uint32_t *src = Tn + (int64_t)64 * g * ldn + 64 * g;
     uint32_t raw[64]; // row i, column l = lane: all loads in flight at once
+    if constexpr (DIRECT) {
+        // op(T)(i, lane) from addresses clamped into the m x m matrix (the
+        // loads carry no condition; entries outside are zeroed below)
+        const int lc = min(lane, d.m - 1);
 #pragma unroll
-    for (int i = 0; i < 64; ++i) raw[i] = src[(int64_t)i * ldn + lane];
+        for (int i = 0; i < 64; ++i) {
+            const int ic = min(i, d.m - 1);
+            raw[i] = d.trans ? d.T[(int64_t)lc * d.ldt + ic] : d.T[(int64_t)ic * d.ldt + lc];
+        }
+    } else {
+        const uint32_t *src = Tn + (int64_t)64 * g * ldn + 64 * g;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) raw[i] = src[(int64_t)i * ldn + lane];
+    }
 #pragma unroll
     for (int i = 0; i < 64; ++i) {
-        const double t = i == lane ? 0.0 : (double)center(raw[i], p, half);
+        double t;
+        if constexpr (DIRECT) {
+            const bool in = i < d.m && lane < d.m && (LOWER ? lane < i : lane > i);
+            uint32_t u = in ? raw[i] : 0u;
+            if (d.dinv) u = mulmod(d.dinv[min(i, d.m - 1)], u, p, pinv);
+            t = (double)center(u, p, half);
+        } else {
+            t = i == lane ? 0.0 : (double)center(raw[i], p, half);
+        }
         if (SPLIT) {
             const double th = __builtin_rint(t * (1.0 / 32768.0));
             sT[0][lane][i] = th;
@@ -450,19 +481,44 @@ hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uin
     return hipGetLastError();
 }
 
+namespace {
+
+template <bool DIRECT>
+void launch_inv(dim3 grid, hipStream_t st, const uint32_t *Tn, int64_t ldn, int lower,
+                uint32_t p, int split, uint32_t *Tinv, const InvDirect &d)
+{
+    const double pinv = 1.0 / (double)p;
+    if (split && lower)
+        hipLaunchKernelGGL((k_trsm_inv<true, true, DIRECT>), grid, dim3(64), 0, st, Tn, ldn, p,
+                           pinv, Tinv, d);
+    else if (split)
+        hipLaunchKernelGGL((k_trsm_inv<true, false, DIRECT>), grid, dim3(64), 0, st, Tn, ldn, p,
+                           pinv, Tinv, d);
+    else if (lower)
+        hipLaunchKernelGGL((k_trsm_inv<false, true, DIRECT>), grid, dim3(64), 0, st, Tn, ldn, p,
+                           pinv, Tinv, d);
+    else
+        hipLaunchKernelGGL((k_trsm_inv<false, false, DIRECT>), grid, dim3(64), 0, st, Tn, ldn, p,
+                           pinv, Tinv, d);
+}
+
+} // namespace
+
 hipError_t launch_trsm_inv(const uint32_t *Tn, int64_t ldn, int lower, uint32_t p, int split,
                            uint32_t *Tinv, hipStream_t st)
 {
-    const dim3 grid((unsigned)(ldn / 64 * 4));
-    const double pinv = 1.0 / (double)p;
-    if (split && lower)
-        hipLaunchKernelGGL((k_trsm_inv<true, true>), grid, dim3(64), 0, st, Tn, ldn, p, pinv, Tinv);
-    else if (split)
-        hipLaunchKernelGGL((k_trsm_inv<true, false>), grid, dim3(64), 0, st, Tn, ldn, p, pinv, Tinv);
-    else if (lower)
-        hipLaunchKernelGGL((k_trsm_inv<false, true>), grid, dim3(64), 0, st, Tn, ldn, p, pinv, Tinv);
-    else
-        hipLaunchKernelGGL((k_trsm_inv<false, false>), grid, dim3(64), 0, st, Tn, ldn, p, pinv, Tinv);
+    launch_inv<false>(dim3((unsigned)(ldn / 64 * 4)), st, Tn, ldn, lower, p, split, Tinv,
+                      InvDirect{nullptr, 0, 0, 0, nullptr});
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int lower,
+                                  int64_t m, uint32_t p, int split, const uint32_t *dinv,
+                                  uint32_t *Tinv, hipStream_t st)
+{
+    if (m < 1 || m > 64) return hipErrorInvalidValue;
+    launch_inv<true>(dim3(4), st, nullptr, 0, lower, p, split, Tinv,
+                     InvDirect{T, ldt, trans, (int)m, dinv});
     return hipGetLastError();
 }
 

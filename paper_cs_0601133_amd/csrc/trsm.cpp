@@ -157,7 +157,19 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
         }
     }
     const uint32_t *dv = unit ? nullptr : dinv;
-    FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, ldn, p, dv, Tn, st));
+    // 64-term sums of centered products (|t| <= p/2, |x| <= p/2 + 2) plus a
+    // residual stay exact integers in binary64 up to 2^53
+    const double h = (double)(p / 2), hx = h + 2.0;
+    const int split = !(64.0 * h * hx + hx <= 9007199254740992.0);
+    if (m <= 64) {
+        // one diagonal block: its inverse straight from op(T); the single
+        // leaf reads no T'
+        FF_HIP_CHECK(launch_trsm_inv_direct(T, ldt, transT == FF_TRANS, lower, m, p, split, dv,
+                                            Tinv, st));
+    } else {
+        FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, ldn, p, dv, Tn, st));
+        FF_HIP_CHECK(launch_trsm_inv(Tn, ldn, lower, p, split, Tinv, st));
+    }
     if (alpha != 1 || !unit) FF_HIP_CHECK(launch_trsm_scale(B, ldb, m, n, p, alpha, dv, st));
     Trsm c;
     c.p = p;
@@ -170,11 +182,7 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
     c.B = B;
     c.ldb = ldb;
     c.leaf = trsm_leaf_rows();
-    // 64-term sums of centered products (|t| <= p/2, |x| <= p/2 + 2) plus a
-    // residual stay exact integers in binary64 up to 2^53
-    const double h = (double)(p / 2), hx = h + 2.0;
-    c.split = !(64.0 * h * hx + hx <= 9007199254740992.0);
-    FF_HIP_CHECK(launch_trsm_inv(Tn, ldn, lower, p, c.split, Tinv, st));
+    c.split = split;
     c.o = o;
     c.o.stream = (void *)st;
     c.o.validate = 0;

@@ -125,3 +125,19 @@ def test_trsm_leaf_sizes(monkeypatch, p, leaf):
         B = synth.residues(synth.seed_for(102, 2), (m, n), p)
         got = solve_gpu(p, T, B, 7, lower, 1, 0)
         assert np.array_equal(got, oracle.ftrsm(p, T, B, 7, lower, trans=True)), lower
+
+
+@pytest.mark.parametrize("p", [65521, 2147483647], ids=["binary64", "split"])
+def test_trsm_single_block_read_in_place(p):
+    # m <= 64: the inverse of the one diagonal block is formed straight from
+    # op(T) (no normalised copy); T sits in a wider buffer (ldt = m + 3) and
+    # is read transposed, upper and lower, unit and not
+    m, n = 37, 50
+    T = tri(p, m, 103)
+    Tw = np.full((m, m + 3), p - 1, np.uint32); Tw[:, :m] = T
+    B = synth.residues(synth.seed_for(104, 2), (m, n), p)
+    for lower, unit in itertools.product((0, 1), (0, 1)):
+        dT, dB = to_dev(Tw), to_dev(B)
+        ff.ftrsm(p, dT[:, :m], dB, 6, lower, True, unit)
+        want = oracle.ftrsm(p, T, B, 6, lower, True, unit)
+        assert np.array_equal(from_dev(dB), want), (lower, unit)
