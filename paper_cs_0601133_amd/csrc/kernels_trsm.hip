@@ -131,11 +131,12 @@ __device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 // subtracted, and is then subtracted, times T'(i, l), from every other row
 // (T' is read with its diagonal set to 0, and it is 0 on the far side of the
 // triangle, so no row needs a test).  One wave takes 16 columns of one
-// block; lane (j, rl) keeps rows rl + 4q, q < 16, of its column in registers,
-// unreduced: each is a sum of at most 63 products of centered values, exact
-// in binary64 under the bound of the leaf solve (SPLIT: the entries of T'
-// cut in two as there).  Row l, reduced, reaches the lanes of its column by
-// a shuffle: no barrier inside the 64 steps.
+// block; lane 4 jl + rl keeps rows rl + 4q, q < 16, of column 16 jq + jl in
+// registers, unreduced: each is a sum of at most 63 products of centered
+// values, exact in binary64 under the bound of the leaf solve (SPLIT: the
+// entries of T' cut in two as there).  Row l, reduced, reaches the four
+// lanes of its column by a DPP quad broadcast (a register move, no LDS
+// round trip): no barrier and no memory access on the 64-step chain.
 //
 // DIRECT (systems of at most 64 rows, whose one leaf reads no T'): the
 // entries come straight from op(T) (InvDirect), restricted to the triangle
@@ -148,6 +149,16 @@ struct InvDirect {
     const uint32_t *dinv; // null: unit diagonal
 };
 
+// v of lane 4 (lane / 4) + R, to every lane of its quad.
+template <int R>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    constexpr int ctrl = R | (R << 2) | (R << 4) | (R << 6); // quad_perm [R, R, R, R]
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 template <bool SPLIT, bool LOWER, bool DIRECT>
 __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn, uint32_t p,
                                                  double pinv, uint32_t *Tinv, InvDirect d)
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
     // transposing stores (one l per lane) spread over the banks
     __shared__ double sT[SPLIT ? 2 : 1][64][65];
     const int g = blockIdx.x >> 2, jq = blockIdx.x & 3;
-    const int lane = threadIdx.x, jl = lane & 15, rl = lane >> 4;
+    const int lane = threadIdx.x, jl = lane >> 2, rl = lane & 3;
     const int j = 16 * jq + jl;
     const uint32_t half = (p - 1) / 2;
     const double pd = (double)p;
@@ -212,7 +223,13 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
         v = reduce_c(v, pd, pinv);
         y[qo] = v;
         yh[qo] = 0.0;
-        const double yl = __shfl(v, jl + 16 * ro, 64);
+        double yl;
+        switch (ro) { // a constant once the loop is unrolled
+        case 0: yl = quad_bcast<0>(v); break;
+        case 1: yl = quad_bcast<1>(v); break;
+        case 2: yl = quad_bcast<2>(v); break;
+        default: yl = quad_bcast<3>(v); break;
+        }
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = rl + 4 * q;
