@@ -173,14 +173,12 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
     const double pd = (double)p;
     uint32_t raw[64]; // row i, column l = lane: all loads in flight at once
     if constexpr (DIRECT) {
-        // op(T)(i, lane) from addresses clamped into the m x m matrix (the
-        // loads carry no condition; entries outside are zeroed below)
+        // T(i, lane) from addresses clamped into the m x m matrix (the loads
+        // carry no condition and run along rows of T; entries outside are
+        // zeroed below).  It is op(T)(i, lane), or op(T)(lane, i) if trans.
         const int lc = min(lane, d.m - 1);
 #pragma unroll
-        for (int i = 0; i < 64; ++i) {
-            const int ic = min(i, d.m - 1);
-            raw[i] = d.trans ? d.T[(int64_t)lc * d.ldt + ic] : d.T[(int64_t)ic * d.ldt + lc];
-        }
+        for (int i = 0; i < 64; ++i) raw[i] = d.T[(int64_t)min(i, d.m - 1) * d.ldt + lc];
     } else {
         const uint32_t *src = Tn + (int64_t)64 * g * ldn + 64 * g;
 #pragma unroll
@@ -189,20 +187,22 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
 #pragma unroll
     for (int i = 0; i < 64; ++i) {
         double t;
+        int row = i, col = lane; // of T', where t goes
         if constexpr (DIRECT) {
-            const bool in = i < d.m && lane < d.m && (LOWER ? lane < i : lane > i);
+            if (d.trans) { row = lane; col = i; }
+            const bool in = row < d.m && col < d.m && (LOWER ? col < row : col > row);
             uint32_t u = in ? raw[i] : 0u;
-            if (d.dinv) u = mulmod(d.dinv[min(i, d.m - 1)], u, p, pinv);
+            if (d.dinv) u = mulmod(d.dinv[min(row, d.m - 1)], u, p, pinv);
             t = (double)center(u, p, half);
         } else {
             t = i == lane ? 0.0 : (double)center(raw[i], p, half);
         }
         if (SPLIT) {
             const double th = __builtin_rint(t * (1.0 / 32768.0));
-            sT[0][lane][i] = th;
-            sT[SPLIT ? 1 : 0][lane][i] = __builtin_fma(-th, 32768.0, t);
+            sT[0][col][row] = th;
+            sT[SPLIT ? 1 : 0][col][row] = __builtin_fma(-th, 32768.0, t);
         } else {
-            sT[0][lane][i] = t;
+            sT[0][col][row] = t;
         }
     }
     double y[16], yh[16];
