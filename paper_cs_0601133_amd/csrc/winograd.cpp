@@ -230,7 +230,21 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
                 return rc;
             FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_wino_slice(w[0], w[1], st)));
         }
-        if ((rc = launch_batch(bp, ctr, st, 0, !fused))) return rc;
+        if (P.path == FF_PATH_INT8 && bp.scales.empty() && bp.singles.empty() && !bp.ij.empty()) {
+            // leaves of one size: one workgroup per tile (XCD-aware order),
+            // no work queue
+            char *bw = bp.bound_ws;
+            if (!fused)
+                FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st,
+                                      launch_slice_batched((const SliceJob *)(bw + bp.off_sj),
+                                                           (int)bp.sj.size(), bp.slice_blocks,
+                                                           st)));
+            FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st,
+                                  launch_i8_jobs(bp.tile, (const I8Job *)(bw + bp.off_ij),
+                                                 (int)bp.ij.size(), bp.i8_tiles, st)));
+        } else if ((rc = launch_batch(bp, ctr, st, 0, !fused))) {
+            return rc;
+        }
     }
 
     // Post-additions, level by level up to C.
