@@ -138,12 +138,12 @@ struct Crossover {
 
 // Measured on MI355X (square products, one level against none): INT8
 // leaves of one digit never gain (the digit product costs about what the
-// extra passes move); INT8 leaves of 2..5 digits gain 2-13% from n = 3072
-// on with residues below 2^30, and 2% at 12288 above (wider arithmetic in
-// the fused pre-addition); a second INT8 level loses up to 16384.  FP64
-// leaves gain from n = 2048 (the seven leaf products fill the chip where
-// one product at that order does not) and a second level from leaf order
-// 4096.
+// extra passes move); INT8 leaves of 2..5 digits gain 4-15% from n = 3072
+// on with residues below 2^30, and 3-8% from 8192 on above (wider
+// arithmetic in the fused pre-addition); a second INT8 level gains at most
+// 1% up to 16384.  FP64 leaves gain from n = 2048 (the seven leaf products
+// fill the chip where one product at that order does not) and a second
+// level from leaf order 4096.
 Crossover crossover(int path, int s0, uint32_t p)
 {
     const char *e = std::getenv("FF_WINOGRAD_W");
@@ -151,7 +151,7 @@ Crossover crossover(int path, int s0, uint32_t p)
     constexpr int64_t NEVER = int64_t(1) << 62;
     if (path == FF_PATH_FP64) return {2048, 4096};
     if (s0 <= 1) return {NEVER, NEVER};
-    if (p >= (1u << 30)) return {12288, 24576};
+    if (p >= (1u << 30)) return {8192, 24576};
     return {3072, 12288};
 }
 
