@@ -204,9 +204,10 @@ int launch_batch(BatchPrep &B, unsigned *ctr, hipStream_t st, int persistent, bo
                                                 st)));
     }
     if (B.path == FF_PATH_FP64 && !B.fj.empty()) {
-        FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st,
-                              launch_pack_f64_batched((const SliceJob *)(ws + B.off_sj),
-                                                      (int)B.sj.size(), B.slice_blocks, st)));
+        if (slice)
+            FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st,
+                                  launch_pack_f64_batched((const SliceJob *)(ws + B.off_sj),
+                                                          (int)B.sj.size(), B.slice_blocks, st)));
         const F64Job *tab = (const F64Job *)(ws + B.off_fj);
         const int nf = (int)B.fj.size() - B.fj_fine;
         if (B.fj_fine > 0)

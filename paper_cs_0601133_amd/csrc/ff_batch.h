@@ -44,8 +44,8 @@ struct BatchPrep {
 
 int prep_batch(const std::vector<IJob> &jobs, int path, int tile, BatchPrep *out);
 int upload_batch(BatchPrep &B, char *ws, hipStream_t st, bool sync);
-// slice = false: the digit planes are already written (fused Winograd
-// pre-additions); only the GEMM launch runs.
+// slice = false: the digit planes or packed doubles are already written
+// (fused Winograd pre-additions); only the GEMM launches run.
 int launch_batch(BatchPrep &B, unsigned *ctr, hipStream_t st, int persistent, bool slice = true);
 int job_from_abi(const ff_job &a, const ff_opts &o, IJob *out);
 int run_single_job(const IJob &j, const ff_opts &o, hipStream_t st);

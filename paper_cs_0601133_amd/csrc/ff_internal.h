@@ -343,11 +343,12 @@ struct PostLevel {
 };
 hipError_t launch_postadd(const PostLevel &job, hipStream_t st);
 
-// Last level of pre-additions fused with the digit slicing of the INT8
-// leaves: for each of `count` input blocks, the seven combinations of its
-// four quadrants are formed in registers and sliced straight into the
-// packed digit planes of leaves 7*o .. 7*o + 6 (the values, hence the
-// digits, are those of launch_preadd followed by the slicer).
+// Last level of pre-additions fused with the digit slicing (INT8 leaves) or
+// the binary64 packing (FP64 leaves) of the leaves' operands: for each of
+// `count` input blocks, the seven combinations of its four quadrants are
+// formed in registers and written straight into the packed operands of
+// leaves 7*o .. 7*o + 6 (the values, hence the digits or doubles, are those
+// of launch_preadd followed by the slicer or packer).
 struct WinoSlice {
     SliceJob J;           // reads of quadrant 11 of block 0, packing layout (J.D unused)
     int64_t qoff[4];      // element offset of quadrant 11, 12, 21, 22 from a block's base
@@ -355,8 +356,9 @@ struct WinoSlice {
     int count;            // input blocks
     int side;             // 0: A coefficients, 1: B coefficients
     int reduce;           // reduce each combination to a centered residue
-    int8_t *D;            // digit planes of leaf 0
-    int64_t leaf_stride;  // bytes between the planes of consecutive leaves
+    int8_t *D;            // digit planes (or packed doubles) of leaf 0
+    int64_t leaf_stride;  // bytes between the operands of consecutive leaves
+    int f64;              // packed binary64 (FP64 leaves) instead of digit planes
 };
 int wino_slice_blocks(const WinoSlice &w);
 // Fused last level on (FF_WINO_FUSED=0 turns it off).

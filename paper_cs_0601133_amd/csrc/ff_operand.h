@@ -132,4 +132,18 @@ __device__ __forceinline__ void write_digits(const SliceJob &J, int8_t *D, int32
     }
 }
 
+// Writes the 16 values of unit (r, kc) as binary64 into the packed operand
+// at D (layout of the FP64 packing: element (r, k) at double offset
+// (r/RT)*RT*KP + (k/16)*RT*16 + ((r%RT)/16)*256 + ((k%16)/2)*32 + (r%16)*2 +
+// k%2; 16 consecutive rows write 256 contiguous bytes per 16-byte word).
+__device__ __forceinline__ void write_f64(const SliceJob &J, double *D, const double *v, int r,
+                                          int kc)
+{
+    typedef double v2d_ __attribute__((ext_vector_type(2)));
+    double *dst = D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * 16 +
+                  (int64_t)((r % J.RT) >> 4) * 256 + (r & 15) * 2;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) *(v2d_ *)(dst + c * 32) = v2d_{v[2 * c], v[2 * c + 1]};
+}
+
 } // namespace ff

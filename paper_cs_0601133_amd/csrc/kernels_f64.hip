@@ -51,10 +51,8 @@ __device__ __forceinline__ void pack_block(const SliceJob &J, int b, UnitTile &t
 #pragma unroll
     for (int e = 0; e < F64_BK; ++e)
         v[e] = (double)(J.in_mode == IN_SIGNED ? (int32_t)u[e] : center(u[e], J.p, half));
-    double *dst = (double *)J.D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * F64_BK +
-                  (int64_t)((r % J.RT) >> 4) * 256 + (r & 15) * 2;
-#pragma unroll
-    for (int c = 0; c < F64_BK / 2; ++c) *(v2d *)(dst + c * 32) = v2d{v[2 * c], v[2 * c + 1]};
+    static_assert(F64_BK == 16, "one unit is one K chunk of the packed layout");
+    write_f64(J, (double *)J.D, v, r, kc);
 }
 
 // Both operands of one product in one launch: blocks [0, blocks_a) pack a,

@@ -2,9 +2,10 @@
 // launch.  All are streaming kernels bound by HBM bandwidth: each thread
 // reads the four quadrant values of one position and writes the seven
 // combinations (pre) or reads seven products and writes four quadrants
-// (post).  On the INT8 path the last level of pre-additions is fused with
-// the digit slicing of the leaves (k_wino_slice), so its seven int32
-// combinations never reach memory.
+// (post).  The last level of pre-additions is fused with the digit slicing
+// (INT8 leaves) or the packing into binary64 (FP64 leaves) of the leaves'
+// operands (k_wino_slice), so its seven int32 combinations never reach
+// memory.
 #include <algorithm>
 
 #include "ff_device.h"
@@ -128,9 +129,10 @@ __device__ __forceinline__ int32_t center_mod32(int32_t x, int32_t p, double pd,
 
 // One unit position of one input block: the four quadrant units are read
 // (all loads issued before the LDS transposes when K-contiguous), the seven
-// combinations formed and sliced into the planes of the block's seven
-// leaves.  NARROW: |values| < 2^29, so four-term sums fit int32.
-template <int SIDE, bool NARROW>
+// combinations formed and written to the block's seven leaves: as digit
+// planes (INT8 leaves) or as packed binary64 (F64).  NARROW: |values| <
+// 2^29, so four-term sums fit int32.
+template <int SIDE, bool NARROW, bool F64>
 __device__ __forceinline__ void wino_slice_block(const WinoSlice &W, int b, UnitTile &tile)
 {
     const int ub = unit_blocks(W.J);
@@ -196,21 +198,28 @@ __device__ __forceinline__ void wino_slice_block(const WinoSlice &W, int b, Unit
                 v[e] = (int32_t)(W.reduce ? center_mod(x, W.J.p, pd, pinv) : x);
             }
         }
-        write_digits(W.J, D + (int64_t)t * W.leaf_stride, v, r, kc);
+        if constexpr (F64) {
+            double d[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) d[e] = (double)v[e];
+            write_f64(W.J, (double *)(D + (int64_t)t * W.leaf_stride), d, r, kc);
+        } else {
+            write_digits(W.J, D + (int64_t)t * W.leaf_stride, v, r, kc);
+        }
     }
 }
 
 // Both sides in one launch: blocks [0, blocks_a) take a, the rest b.
-template <bool NARROW>
+template <bool NARROW, bool F64>
 __global__ __launch_bounds__(UNIT_THREADS) void k_wino_slice(WinoSlice a, WinoSlice b,
                                                              int blocks_a)
 {
     __shared__ UnitTile tile;
     const int blk = blockIdx.x;
     if (blk < blocks_a)
-        wino_slice_block<0, NARROW>(a, blk, tile);
+        wino_slice_block<0, NARROW, F64>(a, blk, tile);
     else
-        wino_slice_block<1, NARROW>(b, blk - blocks_a, tile);
+        wino_slice_block<1, NARROW, F64>(b, blk - blocks_a, tile);
 }
 
 // Rows per launch: the y extent of a grid stays within 65535.
@@ -246,12 +255,22 @@ hipError_t launch_wino_slice(const WinoSlice &a, const WinoSlice &b, hipStream_t
     // inputs below 2^29 in magnitude (centered residues of p < 2^30, or the
     // int32 blocks of a reduced previous level) keep four-term sums in int32
     const bool narrow = a.J.p < (1u << 30) && (a.J.in_mode == IN_RESIDUE || a.reduce);
-    if (narrow)
-        hipLaunchKernelGGL(k_wino_slice<true>, dim3((unsigned)(na + nb)), dim3(UNIT_THREADS), 0,
-                           st, a, b, (int)na);
-    else
-        hipLaunchKernelGGL(k_wino_slice<false>, dim3((unsigned)(na + nb)), dim3(UNIT_THREADS), 0,
-                           st, a, b, (int)na);
+    const dim3 grid((unsigned)(na + nb));
+    if (a.f64) {
+        if (narrow)
+            hipLaunchKernelGGL((k_wino_slice<true, true>), grid, dim3(UNIT_THREADS), 0, st, a, b,
+                               (int)na);
+        else
+            hipLaunchKernelGGL((k_wino_slice<false, true>), grid, dim3(UNIT_THREADS), 0, st, a,
+                               b, (int)na);
+    } else {
+        if (narrow)
+            hipLaunchKernelGGL((k_wino_slice<true, false>), grid, dim3(UNIT_THREADS), 0, st, a,
+                               b, (int)na);
+        else
+            hipLaunchKernelGGL((k_wino_slice<false, false>), grid, dim3(UNIT_THREADS), 0, st, a,
+                               b, (int)na);
+    }
     return hipGetLastError();
 }
 

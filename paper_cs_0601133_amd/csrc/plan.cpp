@@ -118,6 +118,18 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 int64_t ipow7(int L) { int64_t r = 1; while (L--) r *= 7; return r; }
 
+// Winograd buffers of the leaf problem (ml x kl times kl x nl, 7^L leaves):
+// int32 combinations of both sides for every level but a fused last one
+// (two ping-pong sets once L > 1), and the products' two sets.
+int64_t wino_buffers(int64_t ml, int64_t nl, int64_t kl, int L, bool one_pass)
+{
+    const int64_t nleaf = ipow7(L);
+    const int64_t szA = round_up(nleaf * ml * kl * 4, 256), szB = round_up(nleaf * kl * nl * 4, 256),
+                  szP = round_up(nleaf * ml * nl * 4, 256);
+    const bool fused = one_pass && wino_fused_enabled();
+    return (fused ? 0 : szA + szB) + (L > 1 ? szA + szB + szP : 0) + szP;
+}
+
 // Tile configuration for the INT8 kernel: FF_I8_TILE (an id of the right
 // slice count) overrides; else the autotuner's cache; else the default.
 int choose_i8_tile(int S, int64_t m, int64_t n, int64_t k, const ff_opts &)
@@ -308,15 +320,7 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         const int64_t mp = round_up(std::max<int64_t>(ml, 1), t.bm());
         const int64_t np = round_up(std::max<int64_t>(nl, 1), t.bn());
         ws += nleaf * P.slices * (mp + np) * KP;
-        if (L > 0) {
-            // Winograd buffers: int32 combinations of both sides (the last
-            // level's only when not fused into the slicing) and products
-            const int64_t szA = round_up(nleaf * ml * kl * 4, 256),
-                          szB = round_up(nleaf * kl * nl * 4, 256),
-                          szP = round_up(nleaf * ml * nl * 4, 256);
-            const bool fused = kpass == kl && wino_fused_enabled();
-            ws += (fused ? 0 : szA + szB) + (L > 1 ? szA + szB + szP : 0) + szP;
-        }
+        if (L > 0) ws += wino_buffers(ml, nl, kl, L, kpass == kl);
     } else {
         // packed double operands of every leaf
         const F64Tile &t = f64_tile(P.tile);
@@ -325,7 +329,7 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         const int64_t np = round_up(std::max<int64_t>(nl, 1), t.bn());
         ws += nleaf * (mp + np) * KP * 8;
         if (L > 0) {
-            ws += nleaf * (ml * kl + kl * nl) * 4 + nleaf * ml * nl * 4 + 256;
+            ws += wino_buffers(ml, nl, kl, L, true);
         } else if (f64_small(m, n, k)) {
             P.small = 1;
             ws = 0; // residues are read in place

@@ -23,10 +23,12 @@
 // products added afterwards (the dynamic peeling of Appendix A, done once
 // for all levels).
 //
-// On the INT8 path with the leaf K in one int32 pass, the last level of
-// pre-additions is fused with the digit slicing of the leaves: the seven
-// combinations of each quadrant quadruple are sliced in registers straight
-// into the leaves' packed planes (FF_WINO_FUSED=0 runs them apart).
+// With the leaf K in one pass (always on FP64 leaves, within the int32
+// block on INT8 ones), the last level of pre-additions is fused with the
+// preparation of the leaves' operands: the seven combinations of each
+// quadrant quadruple are sliced into digit planes (INT8) or packed as
+// binary64 (FP64) in registers, straight into the leaves' operands
+// (FF_WINO_FUSED=0 runs them apart).
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -70,7 +72,8 @@ int fused_slices(const BatchPrep &bp, char *ws, int L, int transA, int transB, i
                  int64_t ldb, const void *const lastIn[2], int reduce, WinoSlice w[2])
 {
     const int64_t nleaf = pow7(L);
-    if ((int64_t)bp.sj.size() != 2 * nleaf || (int64_t)bp.ij.size() != nleaf)
+    const int64_t njobs = bp.path == FF_PATH_INT8 ? (int64_t)bp.ij.size() : (int64_t)bp.fj.size();
+    if ((int64_t)bp.sj.size() != 2 * nleaf || njobs != nleaf)
         return fail(FF_EUNSUPPORTED, "fused Winograd slicing: unexpected leaf batch");
     const intptr_t a0 = (intptr_t)bp.sj[0].D, b0 = (intptr_t)bp.sj[1].D;
     const intptr_t stride = nleaf > 1 ? (intptr_t)bp.sj[2].D - a0 : 0;
@@ -85,6 +88,7 @@ int fused_slices(const BatchPrep &bp, char *ws, int L, int transA, int transB, i
         W.J = bp.sj[side];
         W.side = side;
         W.reduce = reduce;
+        W.f64 = bp.path == FF_PATH_FP64;
         W.D = (int8_t *)(planes + (side ? b0 : a0));
         W.leaf_stride = (int64_t)stride;
         W.count = (int)(nleaf / 7);
@@ -134,7 +138,7 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
     // passes when an int32 pass cannot hold the whole leaf K (INT8 path).
     const int64_t kpass = P.path == FF_PATH_INT8 ? std::min<int64_t>(kl, P.kblock) : kl;
     const int npass = (int)((kl + kpass - 1) / kpass);
-    const bool fused = P.path == FF_PATH_INT8 && npass == 1 && wino_fused_enabled();
+    const bool fused = npass == 1 && wino_fused_enabled();
 
     // workspace layout (fused: the last level's combinations, which would
     // land in buffer 0, are never stored)

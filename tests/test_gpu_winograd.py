@@ -2,9 +2,10 @@
 
 Covers 1 and 2 levels, delayed (unreduced) and reduced pre-additions,
 dimensions that are not multiples of 2^l (peeling), alpha/beta and
-transposes, the INT8 path with its last pre-addition level fused into the
-digit slicing (the default) and kept apart (FF_WINO_FUSED=0), and the
-8192^3 product at p = 8388593 (sampled + Freivalds).
+transposes, the last pre-addition level fused into the digit slicing (INT8)
+or the binary64 packing (FP64) of the leaves (the default) and kept apart
+(FF_WINO_FUSED=0), and the 8192^3 product at p = 8388593 (sampled +
+Freivalds).
 """
 import numpy as np
 import pytest
@@ -24,8 +25,9 @@ CASES = [
 
 @pytest.mark.parametrize("path,bits,fused", [(ff.FF_PATH_INT8, 7, "1"), (ff.FF_PATH_INT8, 8, "1"),
                                              (ff.FF_PATH_INT8, 7, "0"), (ff.FF_PATH_INT8, 8, "0"),
-                                             (ff.FF_PATH_FP64, 0, "1")],
-                         ids=["int8d7", "int8d8", "int8d7_apart", "int8d8_apart", "fp64"])
+                                             (ff.FF_PATH_FP64, 0, "1"), (ff.FF_PATH_FP64, 0, "0")],
+                         ids=["int8d7", "int8d8", "int8d7_apart", "int8d8_apart", "fp64",
+                              "fp64_apart"])
 @pytest.mark.parametrize("mode", [1, 2], ids=["delayed", "reduced"])
 def test_winograd_levels(path, bits, fused, mode, monkeypatch):
     monkeypatch.setenv("FF_WINO_FUSED", fused)
@@ -63,17 +65,17 @@ def test_winograd_full_size_8192(L, path, bits):
 
 
 def test_winograd_rows_beyond_one_launch():
-    # FP64 leaves with one level at m = 65540: the pre- and post-addition
-    # kernels cover the 32770 quadrant rows in two launches of at most
-    # 32768 rows each (the grid's y extent); an odd trailing row pair and
-    # a peeled last row are covered too (65541 rows)
-    for m in (65540, 65541):
+    # FP64 leaves with two levels at m = 131076: the first level's
+    # pre-additions (65538 quadrant rows) and both levels' post-additions
+    # (32769 and 65538 rows) are split into launches of at most 32768 rows
+    # (the grid's y extent); 131077 rows also peel a last row
+    for m in (131076, 131077):
         p, n, k = 65521, 64, 64
         A = synth.residues(synth.seed_for(80, 1), (m, k), p)
         B = synth.residues(synth.seed_for(80, 2), (k, n), p)
         C = synth.residues(synth.seed_for(80, 3), (m, n), p)
-        o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=1)
-        assert ff.ff_plan_query(p, 0, 0, m, n, k, o).winograd_levels == 1
+        o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=2)
+        assert ff.ff_plan_query(p, 0, 0, m, n, k, o).winograd_levels == 2
         dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
         ff.fgemm(p, dA, dB, dC, 2, 7, opts=o)
         want = oracle.fgemm(p, A, B, C, 2, 7)
