@@ -8,7 +8,9 @@ digit-pair products on INT8 matrix cores with int32 sums, and the epilogue
 that recombines the digits modulo p and applies alpha and beta.  The metric
 is 2mnk / t (Gop/s); the same workload is also timed on the FP64
 matrix-core path (operands packed as centered doubles, reduction every 512
-products) and with 8-bit digits (3 slices).
+products), with 8-bit digits (3 slices), and with one Winograd level on the
+7-bit path (reported beside the plain product as effective 2mnk / t, never
+as the headline value).
 
 The JSON line also carries the roofline of the dominant kernel (the INT8
 digit GEMM, timed with HIP events around its launches), the CPU oracle timed
@@ -195,6 +197,14 @@ def headline(torch, ff, args):
         r["effective_frac_fp64_peak"] = ops / ms / 1e9 / PEAK_FP64_TFLOPS
         res[name] = r
         log(f"4096 {name}: {ms:.3f} ms/step, {r['gops']:.0f} Gop/s")
+    # the same product with one Winograd level (seven half-size digit
+    # products, Section 3.2), beside the plain path: effective 2mnk/t
+    o = ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7, winograd_levels=1)
+    ms, per, _ = time_calls(torch, lambda: ff.fgemm(P, dA, dB, dC, ALPHA, BETA, opts=o),
+                            args.steps, args.warmup)
+    res["int8_d7_winograd1"] = {"ms_per_step": ms, "gops_effective": gops(ops, ms),
+                                **summarize(per)}
+    log(f"4096 int8_d7_winograd1: {ms:.3f} ms/step, {gops(ops, ms):.0f} Gop/s (2mnk/t)")
     return res, (A, B, C)
 
 
