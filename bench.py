@@ -22,6 +22,7 @@ factorisation (Section 5.1), the symmetric product A D A^T (Section 6) and
 the Poisson serving stream.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import math
@@ -220,6 +221,19 @@ def small_latency(torch, ff, args):
         ms, per, _ = time_calls(torch, lambda: ff.fgemm(p, dA, dB, dC, 1, 0, opts=opts),
                                 max(50, args.steps), args.warmup)
         out[name] = {"gops": gops(2.0 * n ** 3, ms), **summarize(per)}
+        # the same calls made straight on the C entry point with arguments
+        # marshalled once: the library's latency without the Python
+        # binding's per-call argument handling
+        lib = ff.load()
+        cargs = (p, 0, 0, n, n, n, 1, dA.data_ptr(), n, dB.data_ptr(), n, 0, dC.data_ptr(), n,
+                 ctypes.byref(opts))
+        if lib.ff_fgemm_ex(*cargs) != ff.FF_OK:
+            raise RuntimeError(lib.ff_last_error().decode())
+        ms, per, _ = time_calls(torch, lambda: lib.ff_fgemm_ex(*cargs), max(50, args.steps),
+                                args.warmup)
+        out[name]["c_entry_point"] = summarize(per)
+        log(f"256 {name}: p50 {out[name]['p50_ms'] * 1e3:.1f} us through the binding, "
+            f"{out[name]['c_entry_point']['p50_ms'] * 1e3:.1f} us on the C entry point")
     return out
 
 

@@ -175,7 +175,7 @@ Crossover crossover(int path, int s0, uint32_t p)
 bool f64_small(int64_t m, int64_t n, int64_t k)
 {
     // the kernel's limits: int dimensions, at most 65535 tile rows
-    if (m > int64_t(65535) * 32 || n > 0x3FFFFFFF || k > 0x3FFFFFFF) return false;
+    if (m > int64_t(65535) * 16 || n > 0x3FFFFFFF || k > 0x3FFFFFFF) return false;
     const char *e = std::getenv("FF_F64_SMALL");
     if (e && *e == '0') return false;
     if (e && *e == '1') return true;
