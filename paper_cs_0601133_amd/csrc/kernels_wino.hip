@@ -18,13 +18,18 @@ namespace {
 
 constexpr int WT = 256;
 
-// Quadrant order 11, 12, 21, 22; products P1..P7.
-__constant__ int PRE_A[7][4] = {
-    {1, 0, 0, 0}, {0, 1, 0, 0}, {1, 1, -1, -1}, {0, 0, 0, 1},
-    {0, 0, 1, 1}, {-1, 0, 1, 1}, {1, 0, -1, 0}};
-__constant__ int PRE_B[7][4] = {
-    {1, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}, {1, -1, -1, 1},
-    {-1, 1, 0, 0}, {1, -1, 0, 1}, {0, -1, 0, 1}};
+// Coefficients of the seven combinations, quadrant order 11, 12, 21, 22,
+// products P1..P7 (Appendix A), by side, as compile-time constants so that
+// a combination is a few adds.
+template <int SIDE>
+__device__ __forceinline__ constexpr int pre_coef(int t, int q)
+{
+    constexpr int a[7][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {1, 1, -1, -1}, {0, 0, 0, 1},
+                             {0, 0, 1, 1}, {-1, 0, 1, 1}, {1, 0, -1, 0}};
+    constexpr int b[7][4] = {{1, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}, {1, -1, -1, 1},
+                             {-1, 1, 0, 0}, {1, -1, 0, 1}, {0, -1, 0, 1}};
+    return SIDE ? b[t][q] : a[t][q];
+}
 
 __device__ __forceinline__ int64_t center_mod(int64_t x, uint32_t p, double pd, double pinv)
 {
@@ -38,6 +43,7 @@ __device__ __forceinline__ int64_t center_mod(int64_t x, uint32_t p, double pd, 
 
 // Grid: x covers the columns of one row of quadrant positions, y the rows
 // from i0 on, z the block o of the previous level, so no thread divides.
+template <int SIDE>
 __global__ __launch_bounds__(WT) void k_preadd(PreLevel J, int i0)
 {
     const int j = blockIdx.x * WT + threadIdx.x;
@@ -62,8 +68,13 @@ __global__ __launch_bounds__(WT) void k_preadd(PreLevel J, int i0)
     int32_t *Y = J.Y + (int64_t)(o * 7) * per + (int64_t)i * J.cols + j;
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
-        const int *cf = J.side ? PRE_B[t] : PRE_A[t];
-        int64_t x = cf[0] * v[0] + cf[1] * v[1] + cf[2] * v[2] + cf[3] * v[3];
+        int64_t x = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cf = pre_coef<SIDE>(t, q);
+            if (cf > 0) x += v[q];
+            if (cf < 0) x -= v[q];
+        }
         if (J.reduce) x = center_mod(x, J.p, pd, pinv);
         Y[(int64_t)t * per] = (int32_t)x;
     }
@@ -101,18 +112,6 @@ __global__ __launch_bounds__(WT) void k_postadd(PostLevel J, int i0)
         }
         *yp = r;
     }
-}
-
-// Coefficients of the seven combinations as compile-time constants (the
-// tables above, by side), so that a combination is a few adds.
-template <int SIDE>
-__device__ __forceinline__ constexpr int pre_coef(int t, int q)
-{
-    constexpr int a[7][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {1, 1, -1, -1}, {0, 0, 0, 1},
-                             {0, 0, 1, 1}, {-1, 0, 1, 1}, {1, 0, -1, 0}};
-    constexpr int b[7][4] = {{1, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}, {1, -1, -1, 1},
-                             {-1, 1, 0, 0}, {1, -1, 0, 1}, {0, -1, 0, 1}};
-    return SIDE ? b[t][q] : a[t][q];
 }
 
 // x mod p, centered, for |x| < 2^31 (binary64 quotient estimate; the
@@ -238,7 +237,10 @@ hipError_t launch_preadd(const PreLevel &J, hipStream_t st)
     if (J.count_in > 65535) return hipErrorInvalidValue;
     for (int i0 = 0; i0 < J.rows; i0 += ROW_CHUNK) {
         const int h = std::min(ROW_CHUNK, J.rows - i0);
-        hipLaunchKernelGGL(k_preadd, grid_of(h, J.cols, J.count_in), dim3(WT), 0, st, J, i0);
+        if (J.side)
+            hipLaunchKernelGGL(k_preadd<1>, grid_of(h, J.cols, J.count_in), dim3(WT), 0, st, J, i0);
+        else
+            hipLaunchKernelGGL(k_preadd<0>, grid_of(h, J.cols, J.count_in), dim3(WT), 0, st, J, i0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
