@@ -73,10 +73,22 @@ enum { FF_NONUNIT = 0, FF_UNIT = 1 };  /* diagonal of T: stored, or all ones */
 enum { FF_PATH_AUTO = 0, FF_PATH_FP64 = 1, FF_PATH_INT8 = 2 };
 
 typedef struct ff_opts {
-    int path;            /* FF_PATH_*                                              */
+    int path;            /* FF_PATH_*.  FF_PATH_AUTO takes INT8, except that a
+                            single product small enough for the one-launch FP64
+                            kernel (m*n <= 512^2, k <= 768; FF_F64_SMALL=0 never,
+                            =1 always) runs on FP64 when no digit width is set
+                            and the FP64 K-block allows p                          */
     int winograd_levels; /* 0..3 recursive levels of Winograd's variant (Section
-                            3.2); -1: automatic, l = floor(log2(n/w)) + 1 with the
-                            crossover order w of Section 3.2.1 (clamped at 0)      */
+                            3.2); -1: automatic, Section 3.2.1's rule with measured
+                            crossover orders: a first level at min(m, n, k) >=
+                            w_first and one more per halving while the leaf order
+                            stays >= w_next, by path and digit count (INT8, one
+                            digit: none; INT8 below p = 2^30: 3072, 12288; INT8
+                            above: 8192, 24576; FP64: 2048, 4096).  FF_WINOGRAD_W=w
+                            sets w_first = w_next = w, i.e. the paper's
+                            l = floor(log2(n/w)) + 1 clamped at 0.  The last level
+                            of pre-additions is fused into the leaves' operand
+                            preparation (FF_WINO_FUSED=0 keeps them apart)         */
     int digit_bits;      /* INT8 path digit width, 7 or 8; 0: automatic            */
     int validate;        /* nonzero: check that inputs are residues < p first
                             (makes the call synchronous)                           */
