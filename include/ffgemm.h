@@ -72,6 +72,17 @@ enum { FF_NONUNIT = 0, FF_UNIT = 1 };  /* diagonal of T: stored, or all ones */
  * recombined modulo p in the epilogue. */
 enum { FF_PATH_AUTO = 0, FF_PATH_FP64 = 1, FF_PATH_INT8 = 2 };
 
+/* Environment (read per call; none is needed):
+ *   FF_WINOGRAD_W   single crossover order for the automatic Winograd levels
+ *   FF_WINO_FUSED   0: keep the last level of pre-additions apart from the
+ *                   leaves' slicing/packing
+ *   FF_F64_SMALL    0: never, 1: always use the one-launch FP64 kernel (else
+ *                   by size)
+ *   FF_I8_TILE, FF_F64_TILE   force an INT8 / FP64 tile configuration id
+ *   FF_TRSM_LEAF    rows per ftrsm leaf launch (64..512, a multiple of 64)
+ *   FF_TUNE_CACHE   autotuner cache file (see ff_autotune)
+ * Every setting gives the same results; only speed changes. */
+
 typedef struct ff_opts {
     int path;            /* FF_PATH_*.  FF_PATH_AUTO takes INT8, except that a
                             single product small enough for the one-launch FP64
