@@ -46,7 +46,7 @@ const F64Tile &f64_tile(int id);
 int f64_default_tile();
 // The configuration the planner uses for an m x n product (FF_F64_TILE
 // overrides; m = n = 0: the batched default).
-int choose_f64_tile(int64_t m = 0, int64_t n = 0);
+int choose_f64_tile(int64_t m = 0, int64_t n = 0, int64_t count = 1);
 // Number of K splits of a single FP64 launch with `tiles` workgroup tiles
 // and nk K stages (1: no split), and the stages per split.
 int f64_splits(int64_t tiles, int64_t nk, int *kt_split);

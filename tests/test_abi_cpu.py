@@ -144,14 +144,22 @@ def test_plan_automatic_path_for_small_products(monkeypatch):
 
 
 def test_plan_fp64_tiles_and_split_k_workspace(monkeypatch):
-    # FP64 products up to 1024 x 1024 take the 128 x 128 tile (id 2), larger
-    # ones the 256 x 128 tile (id 1).  A single launch with fewer than 128
-    # tiles splits K into min(K stages, 512 / tiles) parts; the workspace is
+    # A single launch with fewer than 256 tiles splits K into
+    # min(K stages, 512 / tiles) parts; the workspace is
     # the packed operands (8 bytes per padded element) plus, 256-aligned,
     # one uint32 partial product per split.  (Small products take the
     # one-launch kernel by default; FF_F64_SMALL=0 keeps the general path.)
     monkeypatch.setenv("FF_F64_SMALL", "0")
+    monkeypatch.delenv("FF_F64_TILE", raising=False)
     o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0)
+    # the 256 x 128 tile where its tiles fill whole rounds of one workgroup
+    # per CU (256 CUs), the 128 x 128 tile otherwise; Winograd leaves count
+    # all of a level's products
+    for n, tile in ((2048, 2), (3072, 2), (4096, 1), (6144, 2), (8192, 1)):
+        assert ff.ff_plan_query(8388593, 0, 0, n, n, n, o).tile_config == tile, n
+    for n, L, tile in ((4096, 1, 2), (8192, 1, 1), (8192, 2, 2)):
+        wo = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=L)
+        assert ff.ff_plan_query(8388593, 0, 0, n, n, n, wo).tile_config == tile, (n, L)
     i = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096, o)
     assert i.tile_config == 1
     assert i.workspace_bytes == (4096 + 4096) * 4096 * 8          # 512 tiles: no split
