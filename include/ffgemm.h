@@ -95,7 +95,7 @@ typedef struct ff_opts {
                             w_first and one more per halving while the leaf order
                             stays >= w_next, by path and digit count (INT8, one
                             digit: none; INT8 below p = 2^30: 3072, 12288; INT8
-                            above: 8192, 24576; FP64: 2048, 4096).  FF_WINOGRAD_W=w
+                            above: 8192, 24576; FP64: 3072, 3072).  FF_WINOGRAD_W=w
                             sets w_first = w_next = w, i.e. the paper's
                             l = floor(log2(n/w)) + 1 clamped at 0.  The last level
                             of pre-additions is fused into the leaves' operand

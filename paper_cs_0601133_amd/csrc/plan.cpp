@@ -153,15 +153,15 @@ struct Crossover {
 // extra passes move); INT8 leaves of 2..5 digits gain 4-15% from n = 3072
 // on with residues below 2^30, and 3-8% from 8192 on above (wider
 // arithmetic in the fused pre-addition); a second INT8 level gains at most
-// 1% up to 16384.  FP64 leaves gain from n = 2048 (the seven leaf products
-// fill the chip where one product at that order does not) and a second
-// level from leaf order 4096.
+// 1% up to 16384.  FP64 leaves: one level ties at 2048 and gains 8-40% from
+// 3072 on, a second one gains from leaf order 3072 (the paper's rule with
+// w = 3072).
 Crossover crossover(int path, int s0, uint32_t p)
 {
     const char *e = std::getenv("FF_WINOGRAD_W");
     if (e && std::atoll(e) > 0) return {std::atoll(e), std::atoll(e)};
     constexpr int64_t NEVER = int64_t(1) << 62;
-    if (path == FF_PATH_FP64) return {2048, 4096};
+    if (path == FF_PATH_FP64) return {3072, 3072};
     if (s0 <= 1) return {NEVER, NEVER};
     if (p >= (1u << 30)) return {8192, 24576};
     return {3072, 12288};

@@ -180,7 +180,7 @@ def test_plan_automatic_winograd_levels(monkeypatch):
     # a first level at min(m, n, k) >= w_first, one more per halving while
     # the leaf order stays >= w_next.  INT8 with one digit: never; INT8 with
     # more digits: (3072, 12288) below p = 2^30, (8192, 24576) above;
-    # FP64: (2048, 4096).  FF_WINOGRAD_W = w is the paper's
+    # FP64: (3072, 3072).  FF_WINOGRAD_W = w is the paper's
     # l = floor(log2(n / w)) + 1.
     monkeypatch.delenv("FF_WINOGRAD_W", raising=False)
     i8, f64 = ff.make_opts(path=ff.FF_PATH_INT8), ff.make_opts(path=ff.FF_PATH_FP64)
@@ -192,7 +192,7 @@ def test_plan_automatic_winograd_levels(monkeypatch):
     assert [lv(8388593, n, i8) for n in (3071, 3072, 24575, 24576)] == [0, 1, 1, 2]
     assert lv(8388593, 8192, i8, k=2048) == 0            # the smallest order decides
     assert [lv(2147483647, n, i8) for n in (8191, 8192, 49152)] == [0, 1, 2]
-    assert [lv(65521, n, f64) for n in (2047, 2048, 8191, 8192, 16384)] == [0, 1, 1, 2, 3]
+    assert [lv(65521, n, f64) for n in (3071, 3072, 6143, 6144, 12288)] == [0, 1, 1, 2, 3]
     monkeypatch.setenv("FF_WINOGRAD_W", "5000")
     assert [lv(8388593, n, i8) for n in (4999, 5000, 10000, 20000)] == [0, 1, 2, 3]
     assert lv(251, 5000, i8) == 1
