@@ -60,3 +60,24 @@ def test_small_fp64_beta_zero_and_extreme_residues(monkeypatch):
             got = run(p, A, B, C, 1, 0, False, False)
             want = oracle.fgemm(p, A, B, np.zeros((m, n), np.uint32), 1, 0, False, False)
             assert np.array_equal(got, want), (p, fill)
+
+
+@pytest.mark.parametrize("mode", ["1", "0"], ids=["one_launch", "general"])
+def test_small_fp64_transposed_views_in_wider_buffers(mode, monkeypatch):
+    # op(A) = A^T and op(B) = B^T read from column-sliced views of wider
+    # buffers (lda = m + 11, ldb = k + 3, ldc = n + 6); the padding of C is
+    # not touched
+    monkeypatch.setenv("FF_F64_SMALL", mode)
+    p, m, n, k = 65521, 45, 70, 133
+    A = synth.residues(synth.seed_for(950, 1), (k, m), p)  # op(A) = A^T is m x k
+    B = synth.residues(synth.seed_for(950, 2), (n, k), p)
+    C = synth.residues(synth.seed_for(950, 3), (m, n), p)
+    Aw = np.zeros((k, m + 11), np.uint32); Aw[:, :m] = A
+    Bw = np.zeros((n, k + 3), np.uint32); Bw[:, :k] = B
+    Cw = np.full((m, n + 6), 5, np.uint32); Cw[:, :n] = C
+    dA, dB, dC = to_dev(Aw), to_dev(Bw), to_dev(Cw)
+    ff.fgemm(p, dA[:, :m], dB[:, :k], dC[:, :n], 9, 4, True, True,
+             ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0))
+    got = from_dev(dC)
+    assert np.array_equal(got[:, :n], oracle.fgemm(p, A, B, C, 9, 4, True, True))
+    assert np.all(got[:, n:] == 5)
