@@ -119,15 +119,17 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 int64_t ipow7(int L) { int64_t r = 1; while (L--) r *= 7; return r; }
 
 // Winograd buffers of the leaf problem (ml x kl times kl x nl, 7^L leaves):
-// int32 combinations of both sides for every level but a fused last one
-// (two ping-pong sets once L > 1), and the products' two sets.
+// int32 combinations of both sides in two ping-pong sets (the first only
+// once two levels are stored: unfused, or fused from L = 3 on; the second
+// from L = 2 on), and the products' two sets.
 int64_t wino_buffers(int64_t ml, int64_t nl, int64_t kl, int L, bool one_pass)
 {
     const int64_t nleaf = ipow7(L);
     const int64_t szA = round_up(nleaf * ml * kl * 4, 256), szB = round_up(nleaf * kl * nl * 4, 256),
                   szP = round_up(nleaf * ml * nl * 4, 256);
     const bool fused = one_pass && wino_fused_enabled();
-    return (fused ? 0 : szA + szB) + (L > 1 ? szA + szB + szP : 0) + szP;
+    const bool need0 = !fused || L >= 3;
+    return (need0 ? szA + szB : 0) + (L > 1 ? szA + szB + szP : 0) + szP;
 }
 
 // Tile configuration for the INT8 kernel: FF_I8_TILE (an id of the right

@@ -140,13 +140,15 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
     const int npass = (int)((kl + kpass - 1) / kpass);
     const bool fused = npass == 1 && wino_fused_enabled();
 
-    // workspace layout (fused: the last level's combinations, which would
-    // land in buffer 0, are never stored)
+    // workspace layout.  Stored levels alternate between buffers 0 and 1:
+    // unfused, the last level lands in buffer 0; fused, the last stored level
+    // (L - 1) lands in buffer 1, so buffer 0 is needed only from L = 3 on.
     const int64_t szA = nleaf * ml * kl * 4, szB = nleaf * kl * nl * 4, szP = nleaf * ml * nl * 4;
+    const bool need0 = !fused || L >= 3;
     int64_t off = 0;
-    const int64_t oA0 = off; off = align256(off + (fused ? 0 : szA));
+    const int64_t oA0 = off; off = align256(off + (need0 ? szA : 0));
     const int64_t oA1 = off; off = align256(off + (L > 1 ? szA : 0));
-    const int64_t oB0 = off; off = align256(off + (fused ? 0 : szB));
+    const int64_t oB0 = off; off = align256(off + (need0 ? szB : 0));
     const int64_t oB1 = off; off = align256(off + (L > 1 ? szB : 0));
     const int64_t oP0 = off; off = align256(off + szP);
     const int64_t oP1 = off; off = align256(off + (L > 1 ? szP : 0));
@@ -197,8 +199,10 @@ int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
             // reduced form: reduce at every level (keeps int32 range for any p)
             J.reduce = P.preadds_reduced;
             J.p = p;
-            // levels alternate buffers so that the last one ends in buf[0]
-            J.Y = buf[(L - l) & 1];
+            // levels alternate buffers; the last stored one ends in buf[0]
+            // (unfused) or buf[1] (fused), and no level writes the buffer it
+            // reads
+            J.Y = buf[fused ? (((Lpre - l) & 1) ^ 1) : ((L - l) & 1)];
             FF_HIP_CHECK(launch_preadd(J, st));
             src = J.Y;
             count *= 7;

@@ -80,3 +80,32 @@ def test_winograd_rows_beyond_one_launch():
         ff.fgemm(p, dA, dB, dC, 2, 7, opts=o)
         want = oracle.fgemm(p, A, B, C, 2, 7)
         assert np.array_equal(from_dev(dC), want), m
+
+
+@pytest.mark.parametrize("path,bits,fused", [(ff.FF_PATH_INT8, 7, "1"), (ff.FF_PATH_INT8, 8, "1"),
+                                             (ff.FF_PATH_INT8, 8, "0"), (ff.FF_PATH_FP64, 0, "1"),
+                                             (ff.FF_PATH_FP64, 0, "0")],
+                         ids=["int8d7", "int8d8", "int8d8_apart", "fp64", "fp64_apart"])
+def test_winograd_three_levels(path, bits, fused, monkeypatch):
+    # three levels: the two stored levels of pre-additions alternate between
+    # the workspace's buffers without a level writing the one it reads (the
+    # fused path stores levels 1 and 2, the unfused one all three); odd
+    # sizes peel at every dimension, leaves stay >= 16
+    monkeypatch.setenv("FF_WINO_FUSED", fused)
+    for ci, (p, m, n, k) in enumerate([(8388593, 256, 256, 256), (65521, 300, 270, 333),
+                                       (251, 136, 200, 168)]):
+        tA, tB = bool(ci & 1), bool(ci & 2)
+        A = synth.residues(synth.seed_for(70 + ci, 1), (k, m) if tA else (m, k), p)
+        B = synth.residues(synth.seed_for(70 + ci, 2), (n, k) if tB else (k, n), p)
+        C = synth.residues(synth.seed_for(70 + ci, 3), (m, n), p)
+        o = ff.make_opts(path=path, digit_bits=bits, winograd_levels=3)
+        try:
+            info = ff.ff_plan_query(p, int(tA), int(tB), m, n, k, o)
+        except ff.FFError as e:
+            assert e.status == ff.FF_EUNSUPPORTED
+            continue
+        assert info.winograd_levels == 3
+        dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+        ff.fgemm(p, dA, dB, dC, 6, 2, tA, tB, opts=o)
+        want = oracle.fgemm(p, A, B, C, 6, 2, tA, tB)
+        assert np.array_equal(from_dev(dC), want), (p, m, n, k, tA, tB)
