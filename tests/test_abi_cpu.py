@@ -209,6 +209,12 @@ def test_plan_int8_winograd_workspace(monkeypatch):
     monkeypatch.setenv("FF_WINO_FUSED", "0")
     apart = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096, o).workspace_bytes
     assert apart - fused == 2 * 7 * 2048 * 2048 * 4
+    # from three levels on two sets of int32 combinations are stored either
+    # way (levels 1 and 2 alternate), so the workspace is the same
+    o3 = ff.make_opts(path=ff.FF_PATH_INT8, winograd_levels=3)
+    apart3 = ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096, o3).workspace_bytes
+    monkeypatch.delenv("FF_WINO_FUSED")
+    assert ff.ff_plan_query(8388593, 0, 0, 4096, 4096, 4096, o3).workspace_bytes == apart3
 
 
 @pytest.mark.parametrize("args,msg", [
