@@ -81,3 +81,19 @@ def test_small_fp64_transposed_views_in_wider_buffers(mode, monkeypatch):
     got = from_dev(dC)
     assert np.array_equal(got[:, :n], oracle.fgemm(p, A, B, C, 9, 4, True, True))
     assert np.all(got[:, n:] == 5)
+
+
+@pytest.mark.parametrize("mode", ["1", "0"], ids=["one_launch", "general"])
+def test_small_fp64_fold_after_every_step(mode, monkeypatch):
+    # p = 89999999: (p/2)^2 > 2^50, so the FP64 K-block holds 4..7 products
+    # and the accumulators are reduced after every 4-product matrix-core step
+    monkeypatch.setenv("FF_F64_SMALL", mode)
+    p = 89999999
+    o = ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0)
+    assert 4 <= ff.ff_plan_query(p, 0, 0, 64, 64, 64, o).kblock < 8
+    for si, (m, n, k) in enumerate([(31, 33, 65), (256, 256, 256), (70, 40, 700)]):
+        A = synth.residues(synth.seed_for(960 + si, 1), (m, k), p)
+        B = synth.residues(synth.seed_for(960 + si, 2), (k, n), p)
+        C = synth.residues(synth.seed_for(960 + si, 3), (m, n), p)
+        got = run(p, A, B, C, 5, 3, False, False)
+        assert np.array_equal(got, oracle.fgemm(p, A, B, C, 5, 3)), (m, n, k)
