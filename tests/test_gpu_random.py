@@ -1,4 +1,5 @@
-"""Seeded random configurations of fgemm, bit-exact against the oracle.
+"""Seeded random configurations, bit-exact against the oracle: fgemm, and
+the triangular solve, symmetric product and LQUP built on it.
 
 Each case draws a path (automatic, FP64, INT8 with 7- or 8-bit digits),
 Winograd levels (-1..3), the pre-addition mode, transposes, a modulus from
@@ -64,3 +65,57 @@ def test_random_configurations(block, monkeypatch):
         assert np.array_equal(from_dev(dC), want), c
         ran += 1
     assert ran > 0
+
+
+TRSM_MODULI = [2, 3, 7, 65521, 8388593, 2147483647]
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_random_triangular_solves(block, monkeypatch):
+    # op(T) X = alpha B with random uplo/trans/diag, sizes across the 64-row
+    # block and the 512-row leaf, and the leaf size switch
+    rng = np.random.default_rng(2000 + block)
+    for ci in range(8):
+        p = int(TRSM_MODULI[rng.integers(len(TRSM_MODULI))])
+        m, n = int(rng.integers(1, 700)), int(rng.integers(1, 200))
+        lower, trans, unit = (int(rng.integers(2)) for _ in range(3))
+        alpha = int(rng.integers(1 << 31)) % p
+        monkeypatch.setenv("FF_TRSM_LEAF", str(64 * int(rng.integers(1, 9))))
+        seed = 6000 + 100 * block + ci
+        T = synth.residues(synth.seed_for(seed, 1), (m, m), p)
+        for i in range(m):
+            T[i, i] = 1 + T[i, i] % (p - 1)  # a unit for prime p
+        B = synth.residues(synth.seed_for(seed, 2), (m, n), p)
+        dT, dB = to_dev(T), to_dev(B)
+        ff.ftrsm(p, dT, dB, alpha, lower, trans, unit)
+        want = oracle.ftrsm(p, T, B, alpha, lower, trans, unit)
+        assert np.array_equal(from_dev(dB), want), (p, m, n, lower, trans, unit)
+
+
+@pytest.mark.parametrize("block", range(2))
+def test_random_symmetric_products_and_factorisations(block):
+    rng = np.random.default_rng(3000 + block)
+    for ci in range(6):
+        seed = 7000 + 100 * block + ci
+        # A diag(D) A^T on either path, with and without D
+        p = int([65521, 8388593, 251][rng.integers(3)])
+        m, k = int(rng.integers(1, 400)), int(rng.integers(1, 400))
+        A = synth.residues(synth.seed_for(seed, 1), (m, k), p)
+        d = synth.residues(synth.seed_for(seed, 2), (k,), p) if rng.integers(2) else None
+        C = synth.residues(synth.seed_for(seed, 3), (m, m), p)
+        alpha, beta = int(rng.integers(p)), int(rng.integers(p))
+        path = [ff.FF_PATH_AUTO, ff.FF_PATH_FP64, ff.FF_PATH_INT8][rng.integers(3)]
+        dA, dC = to_dev(A), to_dev(C)
+        dD = to_dev(d) if d is not None else None
+        ff.aat(p, dA, dC, dD, alpha, beta, opts=ff.make_opts(path=path))
+        assert np.array_equal(from_dev(dC), oracle.aat(p, A, d, alpha, beta, C)), (p, m, k)
+        # LQUP against the oracle's factorisation (unique under the pivot
+        # rule); small moduli make dependent rows likely
+        p = int([2, 3, 7, 65521, 8388593][rng.integers(5)])
+        m, n = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        A = synth.residues(synth.seed_for(seed, 4), (m, n), p)
+        dA = to_dev(A)
+        r, piv, perm = ff.lqup(p, dA)
+        F0, r0, piv0, perm0 = oracle.lqup(p, A)
+        assert r == r0 and np.array_equal(perm, perm0) and np.array_equal(piv, piv0), (p, m, n)
+        assert np.array_equal(from_dev(dA), F0), (p, m, n)
