@@ -119,3 +119,40 @@ def test_random_symmetric_products_and_factorisations(block):
         F0, r0, piv0, perm0 = oracle.lqup(p, A)
         assert r == r0 and np.array_equal(perm, perm0) and np.array_equal(piv, piv0), (p, m, n)
         assert np.array_equal(from_dev(dA), F0), (p, m, n)
+
+
+@pytest.mark.parametrize("block", range(3))
+def test_random_batches(block):
+    # one batched launch of jobs with their own modulus, sizes (K = 0 too),
+    # transposes, alpha and beta; every job against the oracle
+    import torch
+    rng = np.random.default_rng(4000 + block)
+    path = [ff.FF_PATH_INT8, ff.FF_PATH_FP64, ff.FF_PATH_AUTO][block]
+    moduli = [2, 251, 65521, 1048573, 8388593] + ([2147483647] if path != ff.FF_PATH_FP64 else [])
+    jobs, abi = [], []
+    for ci in range(int(rng.integers(8, 20))):
+        p = int(moduli[rng.integers(len(moduli))])
+        m, n = int(rng.integers(1, 400)), int(rng.integers(1, 400))
+        k = int(rng.integers(0, 400)) if ci % 7 else 0
+        tA, tB = bool(rng.integers(2)), bool(rng.integers(2))
+        alpha, beta = int(rng.integers(p)), int(rng.integers(p)) if ci % 5 else 0
+        seed = 8000 + 100 * block + ci
+        A = synth.residues(synth.seed_for(seed, 1), (max(k, 1), m) if tA else (m, max(k, 1)), p)
+        B = synth.residues(synth.seed_for(seed, 2), (n, max(k, 1)) if tB else (max(k, 1), n), p)
+        C = synth.residues(synth.seed_for(seed, 3), (m, n), p)
+        dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+        j = ff.job(p, dA, dB, dC, alpha, beta, tA, tB)
+        if k == 0:
+            # the operands stay allocated; the job reads none of them
+            j.k = 0
+            A = A[:0, :] if tA else A[:, :0]
+            B = B[:, :0] if tB else B[:0, :]
+        jobs.append((p, A, B, C, alpha, beta, tA, tB, dC, dA, dB))
+        abi.append(j)
+    ff.ff_set_stream(None)
+    torch.cuda.synchronize()
+    assert ff.ff_fgemm_batched(abi, ff.make_opts(path=path)) == ff.FF_OK, ff.ff_last_error()
+    torch.cuda.synchronize()
+    for (p, A, B, C, alpha, beta, tA, tB, dC, _, _) in jobs:
+        want = oracle.fgemm(p, A, B, C, alpha, beta, tA, tB)
+        assert np.array_equal(from_dev(dC), want), (p, A.shape, B.shape, tA, tB, alpha, beta)
