@@ -17,6 +17,9 @@ Contents
 * ``lqup`` / ``lqup_factors`` / ``det``: the LQUP factorisation of Section
   5.1 by plain row-by-row elimination (first nonzero column as pivot), its
   explicit factors, and the determinant read off U (Section 6).
+* ``inv``: the inverse over Z/p (Section 6 lists it among the routines
+  built on LQUP) as its plain definition, the unique X with A X = I,
+  found by Gauss-Jordan elimination on [A | I]; None when A is singular.
 * ``oracle.bounds``: the paper's accumulation and growth bounds (eq. (1),
   eq. (2), Theorem 3.1, Corollaries 3.2-3.4) in exact Python integers.
 * ``oracle.winograd``: Winograd's variant in exact Python integers (the
@@ -289,6 +292,32 @@ def det(p, A, plant=None):
     for k in range(n):
         d = d * int(F[k, k]) % p
     return d if permutation_sign(perm) > 0 else (p - d) % p
+
+
+def inv(p, A):
+    """A^-1 over Z/p for a square A (p prime), or None when A is singular.
+    Gauss-Jordan on [A | I]: for each column take the first row at or below
+    the diagonal with a nonzero entry, exchange it into place, scale it to a
+    unit pivot and clear the column in every other row.  This is not the
+    LQUP route the library takes; only the result (unique) is shared."""
+    A = np.asarray(A, dtype=np.int64) % p
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("square matrix expected")
+    M = np.concatenate([A, np.eye(n, dtype=np.int64)], axis=1)
+    for c in range(n):
+        nz = np.nonzero(M[c:, c])[0]
+        if nz.size == 0:
+            return None
+        r = c + int(nz[0])
+        if r != c:
+            M[[c, r]] = M[[r, c]]
+        M[c] = M[c] * pow(int(M[c, c]), p - 2, p) % p
+        f = M[:, c].copy()
+        f[c] = 0
+        # entries < p < 2^31, so every product fits in int64
+        M = (M - (f[:, None] * M[c][None, :]) % p) % p
+    return M[:, n:].astype(np.uint32)
 
 
 def aat(p, A, d=None, alpha=1, beta=0, C=None):

@@ -159,3 +159,58 @@ def test_planted_mistake_is_caught():
     A = synth.residues(synth.seed_for(133, 1), (8, 8), p)
     F, r, piv, perm = oracle.lqup(p, A, plant=7)
     assert not check_factorisation(p, A, F, r, piv, perm)
+
+
+def test_inverse_of_every_2x2_over_z5_is_the_adjugate_over_the_determinant():
+    # the closed form [[d, -b], [-c, a]] / (ad - bc); singular exactly when
+    # ad - bc = 0 (mod 5)
+    p = 5
+    for a, b, c, d in itertools.product(range(p), repeat=4):
+        X = oracle.inv(p, [[a, b], [c, d]])
+        dt = (a * d - b * c) % p
+        if dt == 0:
+            assert X is None, (a, b, c, d)
+            continue
+        s = pow(dt, p - 2, p)
+        want = np.array([[d * s % p, (-b) * s % p], [(-c) * s % p, a * s % p]], np.uint32)
+        assert np.array_equal(X, want), (a, b, c, d)
+
+
+@pytest.mark.parametrize("p", [2, 3, 65521, 8388593, 2147483647])
+def test_inverse_is_two_sided_and_an_involution(p):
+    # A X = X A = I through the fgemm oracle, inv(inv(A)) = A; A with a zero
+    # leading entry needs a row exchange
+    n = 37
+    for s in range(4):
+        A = synth.residues(synth.seed_for(700 + s, p % 1000), (n, n), p)
+        A[0, 0] = 0
+        X = oracle.inv(p, A)
+        if X is None:
+            assert oracle.lqup(p, A)[1] < n
+            continue
+        Z = np.zeros((n, n), np.uint32)
+        eye = np.eye(n, dtype=np.uint32)
+        assert np.array_equal(oracle.fgemm(p, A, X, Z), eye)
+        assert np.array_equal(oracle.fgemm(p, X, A, Z), eye)
+        assert np.array_equal(oracle.inv(p, X), A)
+
+
+def test_inverse_special_cases():
+    p = 65521
+    # permutation matrix: the transpose
+    perm = np.random.default_rng(3).permutation(9)
+    P = np.eye(9, dtype=np.uint32)[perm]
+    assert np.array_equal(oracle.inv(p, P), P.T)
+    # diagonal: the entrywise inverses
+    d = np.array([1, 2, 3, p - 1, 40000], np.int64)
+    want = np.diag([pow(int(x), p - 2, p) for x in d]).astype(np.uint32)
+    assert np.array_equal(oracle.inv(p, np.diag(d)), want)
+    # singular: equal rows, a zero column, the zero matrix; 1 x 1
+    A = synth.residues(synth.seed_for(710, 1), (6, 6), p)
+    A[4] = A[1]
+    assert oracle.inv(p, A) is None
+    A = synth.residues(synth.seed_for(711, 1), (6, 6), p)
+    A[:, 2] = 0
+    assert oracle.inv(p, A) is None
+    assert oracle.inv(p, np.zeros((3, 3), np.uint32)) is None
+    assert oracle.inv(p, [[7]])[0, 0] * 7 % p == 1
