@@ -397,6 +397,21 @@ def factorisation(torch, ff, args):
         out[f"n{n}_p{p}"] = {"ms": ms, "rank": ranks[-1],
                              "gops_2n3_3": 2.0 * n ** 3 / 3.0 / ms / 1e6}
         log(f"lqup n={n} p={p}: {ms:.2f} ms, rank {ranks[-1]}")
+        if n == 4096 and p == 8388593:
+            # inverse on the factorisation (Section 6): LQUP, two n x n
+            # triangular solves on the identity, a row permutation; the
+            # operation count of LQUP plus the solves is 2 n^3
+            dX = torch.empty_like(dA0)
+            oks = []
+
+            def inv_step():
+                dA.copy_(dA0)
+                oks.append(ff.inv(p, dA, dX))
+            ms_i, _, _ = time_calls(torch, inv_step, 3, 1)
+            out[f"inv_n{n}_p{p}"] = {"ms": ms_i, "invertible": bool(oks[-1]),
+                                     "gops_2n3": 2.0 * n ** 3 / ms_i / 1e6}
+            log(f"inverse n={n} p={p}: {ms_i:.2f} ms")
+            del dX
         del dA, dA0
     return out
 

@@ -233,6 +233,18 @@ int ff_frank(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
 int ff_fdet(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *det,
             const ff_opts *opts);
 
+/* Inverse over Z/pZ (Section 6, on LQUP), p prime: for square A (device,
+ * n x n, lda >= n, residues < p), X <- A^-1 (device, n x n, ldx >= n), and
+ * *invertible (host) = 1; for singular A, *invertible = 0 and X is not
+ * written.  A is overwritten by its LQUP factorisation (ff_flqup); X may be
+ * A itself or overlap it, since X is written last, from a separate buffer.
+ * The inverse is P U^-1 L^-1: two ff_ftrsm_ex solves on the identity and a
+ * row permutation.  n = 0 gives *invertible = 1; n is at most 65535.  The
+ * call is synchronous.  Workspace: that of ff_flqup and ff_ftrsm, plus
+ * 4 n^2 + 8 n bytes held by the library per stream. */
+int ff_finv(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *X, int64_t ldx,
+            int *invertible, const ff_opts *opts);
+
 /* Symmetric product (Section 6: A x A^T, "with a diagonal in the middle"):
  *
  *     C <- alpha A diag(D) A^T + beta C   (mod p).

@@ -274,6 +274,8 @@ hipError_t launch_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr, int64
 // [skip_lo, skip_hi).
 hipError_t launch_lqup_swap(uint32_t *A, int64_t lda, int64_t m, int64_t skip_lo, int64_t skip_hi,
                             const int64_t *pairs, int npairs, hipStream_t st);
+// Z = I (n x n, row stride n).
+hipError_t launch_lqup_identity(uint32_t *Z, int64_t n, hipStream_t st);
 // U[j][c] = A[rows[j]][c0 + c].
 hipError_t launch_lqup_gather(const uint32_t *A, int64_t lda, const int64_t *rows, int64_t r,
                               int64_t c0, int64_t ncols, uint32_t *U, int64_t ldu, hipStream_t st);

@@ -332,6 +332,23 @@ hipError_t launch_lqup_swap(uint32_t *A, int64_t lda, int64_t m, int64_t skip_lo
     return hipGetLastError();
 }
 
+// Z = I (n x n, row stride n); a grid-stride loop over the entries.
+__global__ __launch_bounds__(256) void k_lqup_identity(uint32_t *Z, int64_t n)
+{
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256)
+        Z[e] = (e / n == e % n) ? 1u : 0u;
+}
+
+hipError_t launch_lqup_identity(uint32_t *Z, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>((n * n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_lqup_identity, dim3(g), dim3(256), 0, st, Z, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_lqup_gather(const uint32_t *A, int64_t lda, const int64_t *rows, int64_t r,
                               int64_t c0, int64_t ncols, uint32_t *U, int64_t ldu, hipStream_t st)
 {

@@ -304,4 +304,51 @@ int ff_fdet(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *det, cons
     return FF_OK;
 }
 
+// A^-1 over Z/pZ (Section 6 builds the inverse on LQUP).  With full rank
+// every row is a pivot row, in order, so A P = L U with (A P)[:, j] =
+// A[:, colperm[j]], and A^-1 = P U^-1 L^-1: solve L Y = I (unit lower
+// triangle of the compressed form), then U Z = Y (its upper triangle), and
+// row colperm[j] of A^-1 is row j of Z.
+int ff_finv(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *X, int64_t ldx,
+            int *invertible, const ff_opts *opts)
+{
+    if (!invertible) return fail(FF_EINVAL, "null output pointer");
+    if (n < 0) return fail(FF_EINVAL, "negative dimension");
+    if (n > 65535) return fail(FF_EINVAL, "n exceeds 65535");
+    if (n > 0 && (!X || ldx < n)) return fail(FF_EINVAL, "X null or ldx < n");
+    *invertible = 0;
+    if (n == 0) {
+        *invertible = 1;
+        return FF_OK;
+    }
+    std::vector<int64_t> piv(n), perm(n);
+    int64_t r = 0;
+    int rc = ff_flqup(p, n, n, A, lda, &r, piv.data(), perm.data(), opts);
+    if (rc) return rc;
+    if (r < n) return FF_OK;
+    ff_opts o = opts ? *opts : default_opts();
+    hipStream_t st = stream_of(&o);
+    o.stream = (void *)st;
+    o.validate = 0;
+    // Z (n x n) and, for each row of A^-1, the row of Z it takes; the
+    // factorisation is finished with this stream's slot-2 buffer
+    const int64_t z_bytes = round_up(n * n * 4, 256);
+    void *ws = nullptr;
+    if ((rc = workspace(st, (size_t)(z_bytes + n * 8), &ws, 2))) return rc;
+    uint32_t *Z = (uint32_t *)ws;
+    int64_t *d_src = (int64_t *)((char *)ws + z_bytes);
+    std::vector<int64_t> src(n);
+    for (int64_t j = 0; j < n; ++j) src[perm[j]] = j;
+    FF_HIP_CHECK(launch_lqup_identity(Z, n, st));
+    FF_HIP_CHECK(hipMemcpyAsync(d_src, src.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
+    if ((rc = ff_ftrsm_ex(p, FF_LOWER, FF_NOTRANS, FF_UNIT, n, n, 1, A, lda, Z, n, &o))) return rc;
+    if ((rc = ff_ftrsm_ex(p, FF_UPPER, FF_NOTRANS, FF_NONUNIT, n, n, 1, A, lda, Z, n, &o)))
+        return rc;
+    FF_HIP_CHECK(launch_lqup_gather(Z, n, d_src, n, 0, n, X, ldx, st));
+    // src is read by the copy above: wait before it goes
+    FF_HIP_CHECK(hipStreamSynchronize(st));
+    *invertible = 1;
+    return FF_OK;
+}
+
 } // extern "C"

@@ -74,6 +74,7 @@ _SIGS = {
     "ff_flqup": ([_U32, _I64, _I64, _VP, _I64, _VP, _VP, _VP, ctypes.POINTER(ff_opts)], _INT),
     "ff_frank": ([_U32, _I64, _I64, _VP, _I64, _VP, ctypes.POINTER(ff_opts)], _INT),
     "ff_fdet": ([_U32, _I64, _VP, _I64, _VP, ctypes.POINTER(ff_opts)], _INT),
+    "ff_finv": ([_U32, _I64, _VP, _I64, _VP, _I64, _VP, ctypes.POINTER(ff_opts)], _INT),
     "ff_plan_query": ([_U32, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ff_opts),
                        ctypes.POINTER(ff_plan_info)], _INT),
     "ff_fgemm_batched": ([ctypes.POINTER(ff_job), _INT, ctypes.POINTER(ff_opts)], _INT),
@@ -245,6 +246,12 @@ def ff_fdet(p, n, A, lda, det, opts=None):
     return load().ff_fdet(p, n, _addr(A), lda, det.ctypes.data, o)
 
 
+def ff_finv(p, n, A, lda, X, ldx, invertible, opts=None):
+    """invertible: numpy int32 array (host) of size 1."""
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_finv(p, n, _addr(A), lda, _addr(X), ldx, invertible.ctypes.data, o)
+
+
 def ff_plan_query(p, transA, transB, m, n, k, opts=None):
     info = ff_plan_info()
     o = ctypes.byref(opts) if opts is not None else None
@@ -400,6 +407,20 @@ def det(p, A, opts=None):
     d = np.zeros(1, dtype=np.uint32)
     _check(ff_fdet(p, A.shape[0], A, _ld(A, 1), d, opts))
     return int(d[0])
+
+
+def inv(p, A, X, opts=None):
+    """X <- A^-1 over Z/p for the square torch tensor A (A is overwritten by
+    its LQUP factorisation; X may be A).  Returns False, X untouched, when A
+    is singular."""
+    import numpy as np
+    if opts is None:
+        opts = make_opts()
+    if not opts.stream:
+        opts.stream = _torch_stream()
+    ok = np.zeros(1, dtype=np.int32)
+    _check(ff_finv(p, A.shape[0], A, _ld(A, 1), X, _ld(X, 1), ok, opts))
+    return bool(ok[0])
 
 
 def fgemm(p, A, B, C, alpha=1, beta=0, transA=False, transB=False, opts=None):

@@ -161,3 +161,56 @@ def test_full_size_certificate(n):
         F, r, piv, perm = gpu_lqup(p, R)
         assert r == n // 2
         check_certificate(p, R, F, r, piv, perm, 600, 6)
+
+
+def gpu_inv(p, A, in_place=False, **opts):
+    n = A.shape[0]
+    dA = to_dev(A)
+    dX = dA if in_place else to_dev(np.full((n, n), 0xABCD, np.uint32))
+    ok = ff.inv(p, dA, dX, opts=ff.make_opts(**opts))
+    return ok, from_dev(dX)
+
+
+@pytest.mark.parametrize("path", ["auto", "int8", "fp64"])
+def test_inverse_matches_the_oracle(path):
+    # the inverse is unique: bit-exact against Gauss-Jordan; singular
+    # matrices report it and leave X as it was
+    kw = {} if path == "auto" else {"path": ff.FF_PATH_INT8 if path == "int8" else ff.FF_PATH_FP64}
+    primes = [3, 7, 65521, 8388593] + ([2147483647] if path != "fp64" else [])
+    for pi, p in enumerate(primes):
+        for si, n in enumerate([1, 2, 64, 65, 130, 300]):
+            A = synth.residues(synth.seed_for(1900 + 10 * pi + si, 1), (n, n), p)
+            want = oracle.inv(p, A)
+            ok, X = gpu_inv(p, A, in_place=bool(si & 1), **kw)
+            if want is None:
+                assert not ok, (p, n)
+                if not si & 1:
+                    assert np.all(X == 0xABCD), (p, n)
+            else:
+                assert ok and np.array_equal(X, want), (path, p, n)
+
+
+def test_inverse_of_singular_and_special_matrices():
+    p = 65521
+    for si, (n, r) in enumerate([(80, 79), (80, 0), (200, 100)]):
+        A = known_rank(p, n, n, r, 1950 + si)
+        ok, X = gpu_inv(p, A)
+        assert not ok and np.all(X == 0xABCD), (n, r)
+    perm = np.random.default_rng(1960).permutation(150)
+    P = np.ascontiguousarray(np.eye(150, dtype=np.uint32)[perm])
+    ok, X = gpu_inv(p, P)
+    assert ok and np.array_equal(X, P.T)
+    inv_ok = np.zeros(1, np.int32)
+    assert ff.ff_finv(p, 0, 0, 1, 0, 1, inv_ok) == ff.FF_OK and inv_ok[0] == 1
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_inverse_full_size_sampled_rows(n):
+    # sampled rows of X A against the identity through the fgemm oracle
+    p = 8388593
+    A = synth.residues(synth.seed_for(1970 + n, 1), (n, n), p)
+    ok, X = gpu_inv(p, A)
+    assert ok
+    rows = np.random.default_rng(n).choice(n, 6, replace=False)
+    XA = oracle.fgemm(p, np.ascontiguousarray(X[rows]), A, np.zeros((6, n), np.uint32))
+    assert np.array_equal(XA, np.eye(n, dtype=np.uint32)[rows])
