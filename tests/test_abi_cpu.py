@@ -10,6 +10,7 @@
 import os
 import re
 
+import numpy as np
 import pytest
 
 from oracle import bounds as bd
@@ -238,6 +239,18 @@ def test_empty_product_is_a_no_op_without_device():
     # m == 0 or n == 0 returns before any device call
     assert ff.ff_fgemm(7, 0, 0, 0, 4, 4, 1, None, 4, None, 4, 0, None, 4) == ff.FF_OK
     assert ff.ff_fgemm(7, 0, 0, 4, 0, 4, 1, None, 4, None, 4, 0, None, 4) == ff.FF_OK
+
+
+def test_inverse_argument_checks_without_device():
+    # every check comes before the first device call; n = 0 is invertible
+    ok = np.zeros(1, np.int32)
+    assert ff.ff_finv(7, 0, None, 1, None, 1, ok) == ff.FF_OK and ok[0] == 1
+    for n, ldx, x, msg in ((-1, 4, 8, "negative"), (70000, 70000, 8, "65535"),
+                           (4, 3, 8, "ldx"), (4, 4, None, "null")):
+        assert ff.ff_finv(7, n, 8, 4, x, ldx, ok) == ff.FF_EINVAL
+        assert msg in ff.ff_last_error(), msg
+    rc = ff.load().ff_finv(7, 4, 8, 4, 8, 4, None, None)
+    assert rc == ff.FF_EINVAL and "null output" in ff.ff_last_error()
 
 
 def test_bad_options():
