@@ -156,3 +156,27 @@ def test_random_batches(block):
     for (p, A, B, C, alpha, beta, tA, tB, dC, _, _) in jobs:
         want = oracle.fgemm(p, A, B, C, alpha, beta, tA, tB)
         assert np.array_equal(from_dev(dC), want), (p, A.shape, B.shape, tA, tB, alpha, beta)
+
+
+@pytest.mark.parametrize("block", range(3))
+def test_random_inverses(block):
+    # square matrices of random order, modulus and path, in place or apart;
+    # small moduli make singular ones likely (reported, X untouched)
+    rng = np.random.default_rng(5000 + block)
+    for ci in range(6):
+        seed = 9000 + 100 * block + ci
+        path = [ff.FF_PATH_AUTO, ff.FF_PATH_FP64, ff.FF_PATH_INT8][rng.integers(3)]
+        moduli = [2, 3, 7, 65521, 8388593] + ([2147483647] if path != ff.FF_PATH_FP64 else [])
+        p = int(moduli[rng.integers(len(moduli))])
+        n = int(rng.integers(1, 300))
+        in_place = bool(rng.integers(2))
+        A = synth.residues(synth.seed_for(seed, 1), (n, n), p)
+        dA = to_dev(A)
+        dX = dA if in_place else to_dev(np.full((n, n), 0xABCD, np.uint32))
+        ok = ff.inv(p, dA, dX, opts=ff.make_opts(path=path))
+        want = oracle.inv(p, A)
+        assert ok == (want is not None), (p, n)
+        if ok:
+            assert np.array_equal(from_dev(dX), want), (path, p, n, in_place)
+        elif not in_place:
+            assert np.all(from_dev(dX) == 0xABCD), (p, n)
