@@ -239,8 +239,9 @@ int ff_fdet(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *det,
  * written.  A is overwritten by its LQUP factorisation (ff_flqup); X may be
  * A itself or overlap it, since X is written last, from a separate buffer.
  * The inverse is P U^-1 L^-1: two ff_ftrsm_ex solves on the identity and a
- * row permutation.  n = 0 gives *invertible = 1; n is at most 65535.  The
- * call is synchronous.  Workspace: that of ff_flqup and ff_ftrsm, plus
+ * row permutation, on the path opts->path selects; opts->validate checks
+ * the entries of A first, as in ff_flqup.  n = 0 gives *invertible = 1; n
+ * is at most 65535.  The call is synchronous.  Workspace: that of ff_flqup and ff_ftrsm, plus
  * 4 n^2 + 8 n bytes held by the library per stream. */
 int ff_finv(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *X, int64_t ldx,
             int *invertible, const ff_opts *opts);
