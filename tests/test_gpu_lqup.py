@@ -202,6 +202,13 @@ def test_inverse_of_singular_and_special_matrices():
     assert ok and np.array_equal(X, P.T)
     inv_ok = np.zeros(1, np.int32)
     assert ff.ff_finv(p, 0, 0, 1, 0, 1, inv_ok) == ff.FF_OK and inv_ok[0] == 1
+    # validate rejects entries >= p and writes neither A nor X
+    bad = synth.residues(synth.seed_for(1965, 1), (20, 20), p)
+    bad[7, 11] = p
+    dB, dX = to_dev(bad), to_dev(np.full((20, 20), 0xABCD, np.uint32))
+    rc = ff.ff_finv(p, 20, dB, 20, dX, 20, inv_ok, ff.make_opts(validate=1))
+    assert rc == ff.FF_EINVAL
+    assert np.array_equal(from_dev(dB), bad) and np.all(from_dev(dX) == 0xABCD)
 
 
 @pytest.mark.parametrize("n", [2048, 4096])
