@@ -246,7 +246,7 @@ int ff_fdet(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *det,
 int ff_finv(uint32_t p, int64_t n, uint32_t *A, int64_t lda, uint32_t *X, int64_t ldx,
             int *invertible, const ff_opts *opts);
 
-/* Symmetric product (Section 6: A x A^T, "with a diagonal in the middle"):
+/* Symmetric product (Section 6: the product A x A^T, here with a diagonal D between the factors):
  *
  *     C <- alpha A diag(D) A^T + beta C   (mod p).
  *

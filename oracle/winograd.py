@@ -6,15 +6,13 @@ given a ``Tracker``, counts scalar field operations and records the largest
 magnitude of every intermediate value, so that Table "tab:winolevel" and
 Theorem 3.1 (with its optimality construction) can be checked.
 
-Two evaluation orders are provided:
+Two evaluation orders are provided, both from Appendix A's definitions:
 * ``winograd_mul``: C = A*B through the seven products and fifteen block
-  additions written out in Appendix A (S1..S4, T1..T4, P1..P7, U1..U7).
-* ``schedule_abc``: C <- alpha*A*B + beta*C through the 21-step schedule with
-  three temporaries of Table "tab:schedule:ABC" (Section 3.2.2).  The
-  table's step that forms P4 multiplies A12 by T4; Appendix A defines P4 as
-  A22*T4, and only that reading reproduces alpha*A*B + beta*C.  The flag
-  ``as_printed`` evaluates the table's P4 step as printed, so that a test
-  can show it is wrong.
+  additions S1..S4, T1..T4, P1..P7, U1..U7.
+* ``winograd_abc_appendix``: A*B + beta*C with the beta*C terms folded into
+  four of the products, the evaluation Theorem 3.1 bounds.
+Appendix A defines P4 as A22*T4; the alpha/beta schedule table of Section
+3.2.2 prints A12 in that step, which a test shows cannot be right.
 """
 
 
@@ -188,52 +186,6 @@ def winograd_mul_peeled(A, B, l, tr=None):
         row = classic(_block(A, me, m, 0, k), B, tr)
         C[me] = row[0]
     return C
-
-
-def schedule_abc(A, B, C, alpha, beta, l, tr=None, as_printed=False):
-    """C <- alpha*A*B + beta*C by the 21-step schedule of Table
-    "tab:schedule:ABC" (temporaries X1, X2, X3), recursively for l levels;
-    at l = 0 the classic product.  Returns the new C (the input is not
-    modified)."""
-    m, k = _shape(A)
-    n = len(B[0]) if B else 0
-    if l == 0:
-        P = classic(A, B, tr)
-        out = _add(_scale(P, alpha, tr), _scale(C, beta, tr), tr)
-        return out
-    if m % 2 or k % 2 or n % 2:
-        raise ValueError("odd dimension")
-    A11, A12, A21, A22 = _split(A)
-    B11, B12, B21, B22 = _split(B)
-    C11, C12, C21, C22 = _split(C)
-
-    def rec(X, Y, Z, b):
-        return schedule_abc(X, Y, Z, alpha, b, l - 1, tr, as_printed)
-
-    zero = [[0] * (n // 2) for _ in range(m // 2)]
-    X1 = _add(A21, A22, tr)                    # S1
-    X2 = _add(B12, B11, tr, -1)                # T1
-    X3 = rec(X1, X2, zero, 0)                  # P5 = alpha S1 T1
-    C22 = _add(X3, _scale(C22, beta, tr), tr)  # C22 = P5 + beta C22
-    C12 = _add(X3, _scale(C12, beta, tr), tr)  # C12 = P5 + beta C12
-    X1 = _add(X1, A11, tr, -1)                 # S2 = S1 - A11
-    X2 = _add(B22, X2, tr, -1)                 # T2 = B22 - T1
-    X3 = rec(A11, B11, zero, 0)                # P1 = alpha A11 B11
-    C11 = _add(X3, _scale(C11, beta, tr), tr)  # C11 = P1 + beta C11
-    X3 = rec(X1, X2, X3, 1)                    # U2 = alpha S2 T2 + P1
-    C11 = rec(A12, B21, C11, 1)                # U1 = alpha A12 B21 + C11
-    X1 = _add(A12, X1, tr, -1)                 # S4 = A12 - S2
-    X2 = _add(X2, B21, tr, -1)                 # T4 = T2 - B21
-    C12 = rec(X1, B22, C12, 1)                 # C12 = alpha S4 B22 + C12
-    C12 = _add(X3, C12, tr)                    # U5 = U2 + C12
-    left = A12 if as_printed else A22
-    C21 = rec(left, X2, C21, -beta)            # P4 = alpha A22 T4 - beta C21
-    X1 = _add(A11, A21, tr, -1)                # S3 = A11 - A21
-    X2 = _add(B22, B12, tr, -1)                # T3 = B22 - B12
-    X3 = rec(X1, X2, X3, 1)                    # U3 = alpha S3 T3 + U2
-    C22 = _add(X3, C22, tr)                    # U7 = U3 + C22
-    C21 = _add(X3, C21, tr, -1)                # U6 = U3 - C21
-    return _join(C11, C12, C21, C22)
 
 
 def winograd_abc_appendix(A, B, C, beta, l, tr=None):

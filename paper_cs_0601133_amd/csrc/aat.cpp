@@ -1,5 +1,5 @@
 // Symmetric product C <- alpha A D A^T + beta C over Z/pZ (the A x A^T of
-// Section 6, "even with a diagonal in the middle"; D = I when no diagonal is
+// Section 6, with a diagonal D between the factors; D = I when no diagonal is
 // given).  The result is symmetric, so only the lower triangle is computed
 // and then mirrored: about half the work of the full product, the n^3
 // (classical) of the paper's AAT(n) instead of 2 n^3.

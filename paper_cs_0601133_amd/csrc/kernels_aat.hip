@@ -1,5 +1,5 @@
 // Element-wise kernels of the symmetric product C <- alpha A D A^T + beta C
-// (the A x A^T of Section 6, with a diagonal in the middle): the column
+// (Section 6's A x A^T with a diagonal D between the factors): the column
 // scaling A D and the mirror that copies the computed lower triangle of C
 // into the upper one.
 #include <algorithm>

@@ -1,5 +1,5 @@
 """Pins of the oracle's symmetric product alpha A diag(d) A^T + beta C
-(Section 6, "A x A^T with a diagonal in the middle").
+(Section 6: the symmetric product A x A^T with a diagonal D between the factors).
 
 Checked against the definition evaluated in Python integers (no fgemm), the
 block identity the paper's recursion rests on (splitting A's columns and d

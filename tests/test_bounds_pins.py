@@ -5,8 +5,11 @@
   implementation, counted while it runs, against all 25 printed entries, and
   the level rule l = floor(log2(n/w)) + 1 of Section 3.2.1 against the
   printed optima.
-* Table "tab:schedule:ABC": the 21-step schedule computes alpha*A*B + beta*C
-  exactly (with P4 = A22*T4), and the step as printed does not.
+* Appendix A's P4 = A22*T4 against the A12 printed in the schedule table of
+  Section 3.2.2.
+* eq. (1) and eq. (2) of Section 2.1.2: hand values, the factor of two the
+  centered representation gains, and a brute-force search over every
+  sequence of centered products in a gamma-bit two's-complement register.
 * Theorem 3.1: Appendix A's matrices A_l, B_l reach the bound exactly; random
   and extreme inputs never exceed it; Corollaries 3.2/3.3 are its special
   cases; Corollary 3.4's exact threshold is checked by brute force over k.
@@ -68,18 +71,28 @@ def test_winograd_equals_classic_and_peeling():
             assert wg.winograd_mul_peeled(A, B, l) == wg.classic(A, B)
 
 
-def test_schedule_abc_and_printed_p4_step():
+def test_p4_is_a22_times_t4():
+    # Appendix A: P4 = A22*T4, and U6 = U3 - P4 is the block C21 of A*B.
+    # The alpha/beta schedule table of Section 3.2.2 prints A12 in its P4
+    # step; with that operand U6 is not C21 (reading of a misprint).
     rnd = random.Random(7)
-    for l in (1, 2):
-        n = 4 * l
+    for n in (2, 4, 6):
         A = _rand(n, n, -20, 20, rnd)
         B = _rand(n, n, -20, 20, rnd)
-        C = _rand(n, n, -20, 20, rnd)
-        alpha, beta = 3, -5
-        want = [[alpha * x + beta * c for x, c in zip(r1, r2)]
-                for r1, r2 in zip(wg.classic(A, B), C)]
-        assert wg.schedule_abc(A, B, C, alpha, beta, l) == want
-        assert wg.schedule_abc(A, B, C, alpha, beta, l, as_printed=True) != want
+        A11, A12, A21, A22 = wg._split(A)
+        B11, B12, B21, B22 = wg._split(B)
+        cl = wg.classic
+        S1 = wg._add(A21, A22, None)
+        S2 = wg._add(S1, A11, None, -1)
+        S3 = wg._add(A11, A21, None, -1)
+        T1 = wg._add(B12, B11, None, -1)
+        T2 = wg._add(B22, T1, None, -1)
+        T3 = wg._add(B22, B12, None, -1)
+        T4 = wg._add(T2, B21, None, -1)
+        U3 = wg._add(wg._add(cl(A11, B11), cl(S2, T2), None), cl(S3, T3), None)
+        C21 = wg._add(cl(A21, B11), cl(A22, B21), None)
+        assert wg._add(U3, cl(A22, T4), None, -1) == C21
+        assert wg._add(U3, cl(A12, T4), None, -1) != C21
 
 
 @pytest.mark.parametrize("l", [1, 2, 3, 4])
@@ -200,3 +213,71 @@ def test_slice_counts_and_int32_blocks():
     for l, s in ((1, 4), (2, 4), (3, 5)):
         wl, wh = bd.winograd_leaf_operand_range(lo, hi, lo, hi, l)
         assert bd.slices_needed(wl, wh, 7) == s
+
+
+# --- Section 2.1.2, eq. (1) and eq. (2) -----------------------------------
+
+def test_lambda_hand_values():
+    # eq. (1): lambda*(p-1)^2 < 2^gamma; eq. (2): lambda*((p-1)/2)^2 < 2^(gamma-1)
+    assert bd.lambda_positive(3, 3) == 1        # 1*4 < 8 <= 2*4
+    assert bd.lambda_centered(3, 3) == 3        # 3*1 < 4 <= 4*1
+    assert bd.lambda_positive(5, 6) == 3        # 3*16 < 64 <= 4*16
+    assert bd.lambda_centered(5, 6) == 7        # 7*4 < 32 <= 8*4
+    assert bd.lambda_centered(7, 8) == 14       # 14*9 < 128 <= 15*9
+    assert bd.lambda_centered(11, 10) == 20     # 20*25 < 512 <= 21*25
+
+
+def test_lambda_centered_gains_a_factor_of_two():
+    # Section 2.1.2: the centered representation improves lambda by a factor
+    # of 2 over eq. (1); exactly, lambda_c is 2*lambda or 2*lambda + 1.
+    for p in (3, 5, 7, 11, 101, 251, 65521, 1048573, 8388593, 2147483647):
+        for gamma in (24, 31, 32, 53, 64):
+            lp = bd.lambda_positive(p, gamma)
+            lc = bd.lambda_centered(p, gamma)
+            assert lc in (2 * lp, 2 * lp + 1), (p, gamma)
+
+
+def _wraps(x, gamma):
+    """x stored in a gamma-bit two's-complement register reads back as x?"""
+    lo, hi = -(1 << (gamma - 1)), (1 << (gamma - 1)) - 1
+    return lo <= x <= hi
+
+
+@pytest.mark.parametrize("p,gamma", [(3, 4), (5, 5), (5, 7), (7, 8), (11, 9)])
+def test_lambda_centered_brute_force(p, gamma):
+    # Largest lambda such that summing ANY lambda products of centered
+    # residues in a gamma-bit signed register never leaves its range:
+    # breadth-first over the reachable partial sums.
+    h = (p - 1) // 2
+    prods = {a * b for a in range(-h, h + 1) for b in range(-h, h + 1)}
+    sums = {0}
+    lam = 0
+    while True:
+        nxt = {s + q for s in sums for q in prods}
+        if not all(_wraps(x, gamma) for x in nxt):
+            break
+        sums = nxt
+        lam += 1
+    assert bd.lambda_centered(p, gamma) == lam
+    # and the same search over residues in [0, p-1] with an unsigned gamma-bit
+    # register gives eq. (1)
+    prods = {a * b for a in range(p) for b in range(p)}
+    sums, lam = {0}, 0
+    while True:
+        nxt = {s + q for s in sums for q in prods}
+        if max(nxt) >= 1 << gamma:
+            break
+        sums = nxt
+        lam += 1
+    assert bd.lambda_positive(p, gamma) == lam
+
+
+def test_lambda_centered_and_the_fp64_kblock():
+    # Reading A1: a binary64 value holds every integer of magnitude <= 2^53,
+    # i.e. it acts as a 54-bit signed register in eq. (2)'s sense, so the
+    # K-block of the FP64 path at p = 8388593 is lambda_centered(p, 54) = 512
+    # (the configuration's k_max), while gamma = 53 in eq. (2) gives 256.
+    p = 8388593
+    assert bd.lambda_centered(p, 53) == 256
+    assert bd.lambda_centered(p, 54) == 512
+    assert bd.fp64_kblock((p // 2) ** 2, p) == bd.lambda_centered(p, 54)
