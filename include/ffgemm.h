@@ -45,6 +45,7 @@
 #ifndef FFGEMM_H
 #define FFGEMM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -140,7 +141,8 @@ typedef struct ff_job {
     int64_t ldc;
 } ff_job;
 
-/* Checks that a gfx950 device is current and sets up per-device state.
+/* Checks that a gfx950 device is current and sets up per-device state,
+ * including the device address of ff_fgemm_noalloc's scratch array.
  * Optional: every entry point initialises lazily. */
 int ff_init(void);
 
@@ -167,6 +169,32 @@ int ff_fgemm_ex(uint32_t p, int transA, int transB,
                 const uint32_t *B, int64_t ldb,
                 uint32_t beta, uint32_t *C, int64_t ldc,
                 const ff_opts *opts);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the plain
+ * product of ff_fgemm_ex, same arguments, semantics and results, with its
+ * scratch (digit planes of the INT8 path, packed operands and split-K
+ * partials of the FP64 path, the validate counter) in a static device array
+ * of FF_NOALLOC_SCRATCH_BYTES instead of library-allocated workspace.  Each
+ * device holds its own copy of the array from its first use (ff_init on
+ * that device, else the first call there) until the process ends.  No
+ * hipMalloc, hipFree or allocating library call is made.
+ * Limits: no Winograd levels (automatic means none; opts->winograd_levels
+ * > 0 returns FF_EUNSUPPORTED); a product whose workspace exceeds the array
+ * (ff_plan_query with winograd_levels = 0 reports workspace_bytes; e.g.
+ * 4096^3 fits on the INT8 path, not on the FP64 path) returns FF_EINVAL and
+ * enqueues nothing.  Every call on one device shares that device's array
+ * and leaves its contents behind: calls on one stream are ordered and safe,
+ * calls that overlap on one device (other streams, other threads) race and
+ * give wrong results.  Call ff_init on each device first so that no call
+ * loads the array. */
+#define FF_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int ff_fgemm_noalloc(uint32_t p, int transA, int transB,
+                     int64_t m, int64_t n, int64_t k,
+                     uint32_t alpha, const uint32_t *A, int64_t lda,
+                     const uint32_t *B, int64_t ldb,
+                     uint32_t beta, uint32_t *C, int64_t ldc,
+                     const ff_opts *opts);
 
 /* Triangular system with matrix right-hand side (Section 4):
  *

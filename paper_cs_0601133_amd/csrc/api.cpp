@@ -381,14 +381,18 @@ int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
     return FF_OK;
 }
 
+// counter: device word for the count of bad entries, or null to allocate one
+// for the call.
 int validate_inputs(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
                     const uint32_t *A, int64_t lda, const uint32_t *B, int64_t ldb,
-                    uint32_t beta, const uint32_t *C, int64_t ldc, hipStream_t st)
+                    uint32_t beta, const uint32_t *C, int64_t ldc, hipStream_t st,
+                    unsigned *counter)
 {
-    unsigned *bad = nullptr;
-    FF_HIP_CHECK(hipMalloc(&bad, sizeof(unsigned)));
+    unsigned *bad = counter;
+    if (!bad) FF_HIP_CHECK(hipMalloc(&bad, sizeof(unsigned)));
     unsigned h = 0;
-    hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned), st);
+    // zeroed by a kernel (C <- 0 * C on a 1 x 1 matrix), not a memset node
+    hipError_t e = launch_scale(bad, 1, 1, 1, 2u, 0u, st);
     if (e == hipSuccess && k > 0) {
         e = launch_validate(A, lda, transA ? k : m, transA ? m : k, p, bad, st);
         if (e == hipSuccess) e = launch_validate(B, ldb, transB ? n : k, transB ? k : n, p, bad, st);
@@ -396,7 +400,7 @@ int validate_inputs(uint32_t p, int transA, int transB, int64_t m, int64_t n, in
     if (e == hipSuccess && beta) e = launch_validate(C, ldc, m, n, p, bad, st);
     if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(bad);
+    if (!counter) (void)hipFree(bad);
     if (e != hipSuccess) return fail(FF_EHIP, std::string("validate: ") + hipGetErrorString(e));
     if (h) return fail(FF_EINVAL, std::to_string(h) + " input entries are not residues < p");
     return FF_OK;
@@ -430,7 +434,12 @@ static int plan_call(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts 
 
 extern "C" {
 
-int ff_init(void) { return check_device(); }
+int ff_init(void)
+{
+    int rc = check_device();
+    if (rc == FF_OK) rc = noalloc_setup();
+    return rc;
+}
 
 int ff_finalize(void) { return release_all(); }
 
@@ -468,20 +477,33 @@ int ff_plan_query(uint32_t p, int transA, int transB, int64_t m, int64_t n, int6
     return FF_OK;
 }
 
-int ff_fgemm_ex(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
-                uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
-                int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const ff_opts *opts)
+} // extern "C"
+
+namespace ff {
+
+int fgemm_call(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+               uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
+               int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const ff_opts *opts,
+               void *ws_fixed, size_t ws_fixed_bytes)
 {
     int rc = check_args(p, transA, transB, m, n, k, A, lda, B, ldb, C, ldc);
     if (rc) return rc;
     if (m == 0 || n == 0) return FF_OK;
     ff_opts o = opts ? *opts : default_opts();
+    if (ws_fixed) {
+        // fixed scratch: plain products only (Winograd levels need temporaries)
+        if (o.winograd_levels > 0)
+            return fail(FF_EUNSUPPORTED, "Winograd levels need workspace; this entry point "
+                                         "runs plain products only");
+        o.winograd_levels = 0;
+    }
     if ((rc = check_device())) return rc;
     hipStream_t st = stream_of(&o);
     alpha %= p;
     beta %= p;
     if (o.validate) {
-        rc = validate_inputs(p, transA, transB, m, n, k, A, lda, B, ldb, beta, C, ldc, st);
+        rc = validate_inputs(p, transA, transB, m, n, k, A, lda, B, ldb, beta, C, ldc, st,
+                             (unsigned *)ws_fixed);
         if (rc) return rc;
     }
     if (k == 0 || alpha == 0) {
@@ -506,13 +528,32 @@ int ff_fgemm_ex(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_
         FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_f64_small(J, st)));
         return FF_OK;
     }
-    void *ws = nullptr;
-    if ((rc = workspace(st, (size_t)P.ws_bytes, &ws))) return rc;
+    void *ws = ws_fixed;
+    if (ws_fixed) {
+        if ((size_t)P.ws_bytes > ws_fixed_bytes)
+            return fail(FF_EINVAL, "the product needs " + std::to_string(P.ws_bytes) +
+                                       " bytes of scratch; the fixed scratch holds " +
+                                       std::to_string(ws_fixed_bytes));
+    } else if ((rc = workspace(st, (size_t)P.ws_bytes, &ws))) {
+        return rc;
+    }
     if (P.path == FF_PATH_FP64)
         return run_f64_plain(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                              IN_RESIDUE, P.kblock, P.tile, ws, st);
     return run_i8_plain(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, P,
                         ws, st);
+}
+
+} // namespace ff
+
+extern "C" {
+
+int ff_fgemm_ex(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
+                int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const ff_opts *opts)
+{
+    return fgemm_call(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, opts,
+                      nullptr, 0);
 }
 
 int ff_fgemm(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,

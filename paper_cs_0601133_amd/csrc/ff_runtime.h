@@ -44,6 +44,16 @@ int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
                  uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
                  int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const Plan &P,
                  void *ws, hipStream_t st);
+// The whole ff_fgemm_ex call.  ws_fixed: device scratch of ws_fixed_bytes
+// to use instead of the per-stream workspace (plain products only; a
+// product that needs more is rejected), or null.
+int fgemm_call(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
+               uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
+               int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const ff_opts *opts,
+               void *ws_fixed, size_t ws_fixed_bytes);
+// Device address of the static scratch on the current device (noalloc.cpp);
+// noalloc_setup() looks it up once per device.
+int noalloc_setup();
 // Winograd levels > 0 (winograd.cpp).
 int run_winograd(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
                  uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,

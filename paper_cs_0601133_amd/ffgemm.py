@@ -33,6 +33,8 @@ FF_PATH_INT8 = 2
 FF_PROFILE_GEMM = 1
 FF_PROFILE_PREP = 2
 
+FF_NOALLOC_SCRATCH_BYTES = 128 << 20   # size of ff_fgemm_noalloc's static scratch
+
 _I64 = ctypes.c_int64
 _U32 = ctypes.c_uint32
 _INT = ctypes.c_int
@@ -66,6 +68,8 @@ _SIGS = {
                   _VP, _I64], _INT),
     "ff_fgemm_ex": ([_U32, _INT, _INT, _I64, _I64, _I64, _U32, _VP, _I64, _VP, _I64, _U32,
                      _VP, _I64, ctypes.POINTER(ff_opts)], _INT),
+    "ff_fgemm_noalloc": ([_U32, _INT, _INT, _I64, _I64, _I64, _U32, _VP, _I64, _VP, _I64,
+                          _U32, _VP, _I64, ctypes.POINTER(ff_opts)], _INT),
     "ff_ftrsm": ([_U32, _INT, _INT, _INT, _I64, _I64, _U32, _VP, _I64, _VP, _I64], _INT),
     "ff_ftrsm_ex": ([_U32, _INT, _INT, _INT, _I64, _I64, _U32, _VP, _I64, _VP, _I64,
                      ctypes.POINTER(ff_opts)], _INT),
@@ -210,6 +214,13 @@ def ff_fgemm_ex(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
     o = ctypes.byref(opts) if opts is not None else None
     return load().ff_fgemm_ex(p, transA, transB, m, n, k, alpha, _addr(A), lda, _addr(B),
                               ldb, beta, _addr(C), ldc, o)
+
+
+def ff_fgemm_noalloc(p, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                     opts=None):
+    o = ctypes.byref(opts) if opts is not None else None
+    return load().ff_fgemm_noalloc(p, transA, transB, m, n, k, alpha, _addr(A), lda,
+                                   _addr(B), ldb, beta, _addr(C), ldc, o)
 
 
 def ff_ftrsm(p, uplo, transT, diag, m, n, alpha, T, ldt, B, ldb):
