@@ -347,6 +347,8 @@ int oracle_lqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int6
         }
         const int64_t inv = inv_euclid(ri[k], p);
         if (inv < 0) return -2;
+        /* the rows below the pivot are updated independently of each other */
+#pragma omp parallel for schedule(static) if ((m - i) * (n - k) > (1 << 16))
         for (int64_t i2 = i + 1; i2 < m; ++i2) {
             uint32_t *r2 = A + i2 * lda;
             const u128 f = ((u128)r2[k] * (u128)inv) % P;

@@ -4,10 +4,8 @@ oracle (bit-exact).
 Under the pivoting rule both sides follow (rows in order, first nonzero
 column not yet used) the compressed factorisation, the pivot rows and the
 column permutation are unique, so they are compared element by element.
-At 2048 and 4096, where the oracle's elimination would take minutes, the
-factors must rebuild A on sampled entries computed by the oracle one by one
-and have the echelon structure; a valid factorisation certifies the rank
-and the determinant.
+At 2048 and 4096 (the benchmark's size) the whole factored matrix is
+compared too; the inverse there is checked on sampled rows of X A.
 """
 import numpy as np
 import pytest
@@ -148,18 +146,17 @@ def check_certificate(p, A, F, r, piv, perm, samples, seed):
 
 
 @pytest.mark.parametrize("n", [2048, 4096])
-def test_full_size_certificate(n):
-    # m = n = 4096, p = 8388593 is the benchmark's launch configuration
+def test_full_size_whole_output(n):
+    # m = n = 4096, p = 8388593 is the benchmark's launch configuration;
+    # the whole factored matrix, pivots and permutation against the oracle
     p = 8388593
     A = synth.residues(synth.seed_for(180 + n, 1), (n, n), p)
-    F, r, piv, perm = gpu_lqup(p, A)
-    assert r == n
-    check_certificate(p, A, F, r, piv, perm, 600, 5)
+    assert assert_same(p, A) == n
     # rank deficient at full width: rank n / 2
     if n == 2048:
         R = known_rank(p, n, n, n // 2, 181)
+        assert assert_same(p, R) == n // 2
         F, r, piv, perm = gpu_lqup(p, R)
-        assert r == n // 2
         check_certificate(p, R, F, r, piv, perm, 600, 6)
 
 

@@ -206,15 +206,29 @@ def test_deterministic_and_paths_agree():
     assert np.array_equal(outs[0], oracle.fgemm(p, A, B, C, 3, 5))
 
 
-@pytest.mark.parametrize("opts", PATHS, ids=["fp64", "int8d7", "int8d8"])
+_FULL_4096 = {}
+
+
+def _full_4096():
+    """Inputs of the 4096^3 workload and the oracle's whole product, computed
+    once per session."""
+    if not _FULL_4096:
+        p = 8388593
+        A, B, C = inputs(p, 4096, 4096, 4096, 2)
+        _FULL_4096["args"] = (p, A, B, C)
+        _FULL_4096["want"] = oracle.fgemm(p, A, B, C, 3, 5)
+    return _FULL_4096["args"], _FULL_4096["want"]
+
+
+@pytest.mark.parametrize("opts", PATHS + [dict(path=INT8, digit_bits=7, winograd_levels=1)],
+                         ids=["fp64", "int8d7", "int8d8", "int8d7_winograd1"])
 def test_full_size_4096(opts):
     # m = n = k = 4096, p = 8388593, alpha = 3, beta = 5 (the benchmark's
-    # workload and launch configuration): sampled entries + Freivalds
-    p = 8388593
-    A, B, C = inputs(p, 4096, 4096, 4096, 2)
+    # workload and launch configuration): every entry against the oracle
+    (p, A, B, C), want = _full_4096()
     got = run(p, A, B, C, 3, 5, **opts)
-    err = check_sampled(p, A, B, C, got, 3, 5, count=512, seed=2)
-    assert err is None, err
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{len(bad)} entries differ, first at {tuple(bad[0])}"
 
 
 def test_full_size_8192_p251():
