@@ -312,10 +312,17 @@ int ff_batch_graph_destroy(void *graph);
 
 /* Serving loop.  A server owns a device arena of hbm_budget_bytes for the
  * workspaces of its requests and a thread that admits queued requests while
- * their footprint fits, merges them into persistent batched launches and
- * retires them on completion (continuous batching).  Request matrices stay
- * device-resident and caller-owned until the request is done.  submit
- * returns FF_EBUSY only for a request that can never fit the budget. */
+ * their footprint fits, merges them into persistent batched launches on up
+ * to four streams of its own and retires them on completion (continuous
+ * batching).  Request matrices stay device-resident and caller-owned until
+ * the request is done.  submit returns FF_EBUSY only for a request that can
+ * never fit the budget.  Ordering: submit records an event on the
+ * submitting thread's stream (opts->stream given at create, else the
+ * ff_set_stream stream of the submitting thread) and the request's batch
+ * waits for it, so work enqueued on that stream before the submit (the
+ * writes of A, B, C) is complete before the request reads them.  The
+ * INT8 tile of a batch is the autotuner's choice for its largest product
+ * (the default tiling when nothing is tuned). */
 int ff_server_create(int64_t hbm_budget_bytes, const ff_opts *opts, void **server);
 int ff_server_submit(void *server, const ff_job *job, uint64_t *id);
 int ff_server_poll(void *server, uint64_t id, int *done);
@@ -324,6 +331,21 @@ int ff_server_wait(void *server, uint64_t id);
  * and throughput in Gop/s (sum of 2mnk over the busy interval). */
 int ff_server_stats(void *server, double *p50_ms, double *p99_ms, double *gops,
                     int64_t *completed, int64_t *max_inflight);
+/* Counters of a server's life so far: requests by state, launches, the
+ * most requests merged into one launch and on the device at once, the
+ * memory budget and what is admitted against it, the INT8 tile
+ * configuration of the last INT8 batch (-1 if none) and the number of
+ * stream slots. */
+typedef struct ff_server_info {
+    int64_t submitted, completed, failed, queued, running;
+    int64_t batches;            /* launches (each one persistent batch) */
+    int64_t max_batch_requests; /* most requests merged into one launch */
+    int64_t max_inflight;       /* most requests on the device at once */
+    int64_t hbm_budget, hbm_in_use;
+    int last_i8_tile;
+    int stream_slots;
+} ff_server_info;
+int ff_server_query(void *server, ff_server_info *out);
 int ff_server_destroy(void *server);
 
 /* Autotuner (the self-adapting thresholds of Section 7 applied to kernel

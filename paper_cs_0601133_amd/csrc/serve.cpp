@@ -14,6 +14,10 @@
 // operands and C (4(mk + kn + mn) bytes) plus its share of the batch
 // workspace (digit planes or packed doubles, tables), which comes from a
 // device arena of the budget's size owned by the server.
+// Ordering: submit records an event on the submitting thread's stream (the
+// server's opts.stream, else ff_set_stream's), and the batch that carries
+// the request waits for it, so a request may be submitted right after the
+// kernels that write its A, B or C are enqueued.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -92,6 +96,7 @@ class Arena {
 struct Request {
     IJob job;
     int64_t footprint = 0;
+    hipEvent_t ready = nullptr; // recorded on the submitting stream
     double t_submit = 0, t_done = 0;
     int state = 0; // 0 queued, 1 running, 2 done, 3 failed
     int status = FF_OK;
@@ -132,13 +137,66 @@ struct Server {
     // statistics
     std::vector<double> lat_ms;
     double ops = 0, t_first = -1, t_last = 0;
-    int64_t running_reqs = 0, max_running = 0, completed = 0;
+    int64_t running_reqs = 0, max_running = 0, completed = 0, failed = 0, submitted = 0;
+    int64_t batches = 0, max_batch_seen = 0;
+    int last_tile = -1;
     int max_batch = 256;
+    // events for the submit-to-launch ordering, reused
+    std::vector<hipEvent_t> event_pool;
 
     void run();
     bool retire_locked();
     bool admit_locked();
+    void finish_locked(Request &r, int status, double t);
+    hipEvent_t take_event_locked();
+    void release_resources();
 };
+
+void Server::finish_locked(Request &r, int status, double t)
+{
+    r.state = status == FF_OK ? 2 : 3;
+    r.status = status;
+    r.t_done = t;
+    if (status != FF_OK) ++failed;
+    if (r.ready) {
+        event_pool.push_back(r.ready);
+        r.ready = nullptr;
+    }
+}
+
+hipEvent_t Server::take_event_locked()
+{
+    if (!event_pool.empty()) {
+        hipEvent_t e = event_pool.back();
+        event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Streams, events and the arena: everything create made, whether or not
+// create finished (null handles are skipped).
+void Server::release_resources()
+{
+    for (auto &sl : slots) {
+        if (sl.st) (void)hipStreamSynchronize(sl.st);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.st) (void)hipStreamDestroy(sl.st);
+        sl.st = nullptr;
+        sl.done = nullptr;
+    }
+    for (auto &kv : reqs)
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    event_pool.clear();
+    if (arena_mem) (void)hipFree(arena_mem);
+    arena_mem = nullptr;
+}
 
 static int64_t footprint_of(const IJob &j)
 {
@@ -171,9 +229,7 @@ bool Server::retire_locked()
         const int status = q == hipSuccess ? FF_OK : FF_EHIP;
         for (uint64_t id : it->second.ids) {
             Request &r = reqs[id];
-            r.state = status == FF_OK ? 2 : 3;
-            r.status = status;
-            r.t_done = t;
+            finish_locked(r, status, t);
             lat_ms.push_back((t - r.t_submit) * 1e3);
             ops += 2.0 * (double)r.job.m * (double)r.job.n * (double)r.job.k;
             ++completed;
@@ -220,7 +276,18 @@ bool Server::admit_locked()
         f.slot = slot;
         f.ids = pick;
         f.footprint = fp;
-        int tile = path == FF_PATH_INT8 ? i8_default_tile(Smax) : choose_f64_tile();
+        int tile;
+        if (path == FF_PATH_INT8) {
+            // the autotuner's choice for the batch's largest product, as for
+            // ff_fgemm_batched
+            int64_t bm = 1, bn = 1, bk = 1;
+            for (const IJob &j : jobs)
+                if (j.m * j.n * j.k > bm * bn * bk) { bm = j.m; bn = j.n; bk = j.k; }
+            tile = tuned_i8_tile(Smax, bm, bn, bk);
+            if (tile < 0) tile = i8_batch_tile(Smax);
+        } else {
+            tile = choose_f64_tile();
+        }
         int rc = prep_batch(jobs, path, tile, &f.prep);
         if (rc == FF_OK && !arena.alloc(std::max<int64_t>(f.prep.ws_bytes, 256), &f.arena_off)) {
             // fragmented arena: put the requests back (in order) and wait for
@@ -229,6 +296,12 @@ bool Server::admit_locked()
             break;
         }
         Slot &s = slots[slot];
+        // the batch starts after the writes its requests were submitted behind
+        for (uint64_t id : pick) {
+            const Request &r = reqs[id];
+            if (rc == FF_OK && r.ready && hipStreamWaitEvent(s.st, r.ready, 0) != hipSuccess)
+                rc = fail(FF_EHIP, "hipStreamWaitEvent failed");
+        }
         if (rc == FF_OK) rc = upload_batch(f.prep, arena_mem + f.arena_off, s.st, false);
         unsigned *ctr = nullptr;
         if (rc == FF_OK) rc = counter_buffer(s.st, &ctr);
@@ -237,17 +310,19 @@ bool Server::admit_locked()
             if (rc == FF_OK) rc = run_single_job(j, opts, s.st);
         if (rc == FF_OK && hipEventRecord(s.done, s.st) != hipSuccess) rc = FF_EHIP;
         if (rc != FF_OK) {
+            // kernels already enqueued may still use the batch's range
+            (void)hipStreamSynchronize(s.st);
+            (void)hipGetLastError();
             const double t = now_s();
-            for (uint64_t id : pick) {
-                reqs[id].state = 3;
-                reqs[id].status = rc;
-                reqs[id].t_done = t;
-            }
+            for (uint64_t id : pick) finish_locked(reqs[id], rc, t);
             if (f.arena_off >= 0) arena.release(f.arena_off);
             cv_done.notify_all();
             continue;
         }
         for (uint64_t id : pick) reqs[id].state = 1;
+        ++batches;
+        max_batch_seen = std::max<int64_t>(max_batch_seen, (int64_t)pick.size());
+        if (path == FF_PATH_INT8) last_tile = tile;
         running_reqs += (int64_t)pick.size();
         max_running = std::max(max_running, running_reqs);
         in_use += fp;
@@ -286,21 +361,32 @@ int ff_server_create(int64_t hbm_budget_bytes, const ff_opts *opts, void **serve
     int rc = check_device();
     if (rc) return rc;
     Server *s = new Server();
+    auto undo = [s](int status, const std::string &msg) {
+        (void)hipGetLastError();
+        s->release_resources();
+        delete s;
+        return fail(status, msg);
+    };
     s->opts = opts ? *opts : default_opts();
     s->opts.winograd_levels = 0;
     s->budget = hbm_budget_bytes;
-    FF_HIP_CHECK(hipGetDevice(&s->device));
+    if (hipGetDevice(&s->device) != hipSuccess) return undo(FF_EHIP, "hipGetDevice failed");
     if (hipMalloc(&s->arena_mem, hbm_budget_bytes) != hipSuccess) {
-        delete s;
-        return fail(FF_ENOMEM, "server arena allocation failed");
+        s->arena_mem = nullptr;
+        return undo(FF_ENOMEM, "server arena allocation of " +
+                                   std::to_string(hbm_budget_bytes) + " bytes failed");
     }
     s->arena.reset(hbm_budget_bytes);
     const int nslots = 4;
     s->slots.resize(nslots);
     for (auto &sl : s->slots) {
-        if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
-            return fail(FF_EHIP, "stream/event creation failed");
+        if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess) {
+            sl.st = nullptr;
+            return undo(FF_EHIP, "stream creation failed");
+        }
+        if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            sl.done = nullptr;
+            return undo(FF_EHIP, "event creation failed");
         }
     }
     s->worker = std::thread([s] { s->run(); });
@@ -322,8 +408,16 @@ int ff_server_submit(void *server, const ff_job *job, uint64_t *id)
         return fail(FF_EBUSY, "request footprint " + std::to_string(r.footprint) +
                                   " exceeds the server budget");
     std::lock_guard<std::mutex> lk(s->mu);
+    r.ready = s->take_event_locked();
+    if (!r.ready) return fail(FF_EHIP, "event creation failed");
+    if (hipEventRecord(r.ready, stream_of(&s->opts)) != hipSuccess) {
+        (void)hipGetLastError();
+        s->event_pool.push_back(r.ready);
+        return fail(FF_EHIP, "hipEventRecord on the submitting stream failed");
+    }
     r.t_submit = now_s();
     if (s->t_first < 0) s->t_first = r.t_submit;
+    ++s->submitted;
     const uint64_t rid = s->next_id++;
     s->reqs.emplace(rid, r);
     s->queue.push_back(rid);
@@ -380,6 +474,27 @@ int ff_server_stats(void *server, double *p50_ms, double *p99_ms, double *gops,
     return FF_OK;
 }
 
+int ff_server_query(void *server, ff_server_info *out)
+{
+    if (!server || !out) return fail(FF_EINVAL, "null argument");
+    Server *s = (Server *)server;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->failed = s->failed;
+    out->queued = (int64_t)s->queue.size();
+    out->running = s->running_reqs;
+    out->batches = s->batches;
+    out->max_batch_requests = s->max_batch_seen;
+    out->max_inflight = s->max_running;
+    out->hbm_budget = s->budget;
+    out->hbm_in_use = s->in_use;
+    out->last_i8_tile = s->last_tile;
+    out->stream_slots = (int)s->slots.size();
+    return FF_OK;
+}
+
 int ff_server_destroy(void *server)
 {
     if (!server) return fail(FF_EINVAL, "null argument");
@@ -390,12 +505,7 @@ int ff_server_destroy(void *server)
         s->cv_work.notify_all();
     }
     s->worker.join();
-    for (auto &sl : s->slots) {
-        (void)hipStreamSynchronize(sl.st);
-        (void)hipEventDestroy(sl.done);
-        (void)hipStreamDestroy(sl.st);
-    }
-    (void)hipFree(s->arena_mem);
+    s->release_resources();
     delete s;
     return FF_OK;
 }

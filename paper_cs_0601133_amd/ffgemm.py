@@ -59,6 +59,13 @@ class ff_job(ctypes.Structure):
                 ("B", _VP), ("ldb", _I64), ("C", _VP), ("ldc", _I64)]
 
 
+class ff_server_info(ctypes.Structure):
+    _fields_ = [("submitted", _I64), ("completed", _I64), ("failed", _I64), ("queued", _I64),
+                ("running", _I64), ("batches", _I64), ("max_batch_requests", _I64),
+                ("max_inflight", _I64), ("hbm_budget", _I64), ("hbm_in_use", _I64),
+                ("last_i8_tile", _INT), ("stream_slots", _INT)]
+
+
 # name -> (argtypes, restype)
 _SIGS = {
     "ff_init": ([], _INT),
@@ -94,6 +101,7 @@ _SIGS = {
     "ff_server_stats": ([_VP, ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(_I64), ctypes.POINTER(_I64)], _INT),
+    "ff_server_query": ([_VP, ctypes.POINTER(ff_server_info)], _INT),
     "ff_server_destroy": ([_VP], _INT),
     "ff_autotune": ([_INT, _I64, _I64, _I64, ctypes.POINTER(_INT),
                      ctypes.POINTER(ctypes.c_double)], _INT),
@@ -351,6 +359,12 @@ def ff_profile_read():
                                   ctypes.byref(ns)))
     return {"gemm_ms": g.value, "gemm_launches": ng.value, "slice_ms": s.value,
             "slice_launches": ns.value}
+
+
+def ff_server_query(server):
+    info = ff_server_info()
+    _check(load().ff_server_query(server, ctypes.byref(info)))
+    return info
 
 
 def ff_server_destroy(server):
