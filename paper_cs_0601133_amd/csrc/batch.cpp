@@ -94,6 +94,8 @@ int prep_batch(const std::vector<IJob> &jobs, int path, int tile, BatchPrep *out
         }
         B.slice_blocks = blocks;
         B.i8_tiles = tiles;
+        B.uniform_s = !work.empty();
+        for (const IJob &j : work) B.uniform_s = B.uniform_s && j.S == t.S;
     } else {
         const F64Tile &t = f64_tile(tile);
         // jobs reduced per stage before jobs reduced after every step (two
@@ -201,7 +203,7 @@ int launch_batch(BatchPrep &B, unsigned *ctr, hipStream_t st, int persistent, bo
         FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st,
                               launch_i8_batched(B.tile, (const I8Job *)(ws + B.off_ij),
                                                 (int)B.ij.size(), B.i8_tiles, persistent, ctr,
-                                                st)));
+                                                st, B.uniform_s)));
     }
     if (B.path == FF_PATH_FP64 && !B.fj.empty()) {
         if (slice)
@@ -280,7 +282,7 @@ int prep_abi_batch(const ff_job *jobs, int njobs, const ff_opts &o, BatchPrep *B
     int tile;
     if (path == FF_PATH_INT8) {
         tile = tuned_i8_tile(Smax, big_m, big_n, big_k);
-        if (tile < 0) tile = i8_default_tile(Smax);
+        if (tile < 0) tile = i8_batch_tile(Smax);
     } else {
         tile = choose_f64_tile();
     }

@@ -34,6 +34,7 @@ struct BatchPrep {
     std::vector<F64Job> fj;    // jobs reduced per stage, then jobs reduced per step
     int fj_fine = 0;           // index of the first per-step job in fj
     int slice_blocks = 0, i8_tiles = 0, f64_tiles[2] = {0, 0};
+    bool uniform_s = false;    // INT8: every job has the tile's digit count
     std::vector<IJob> scales;  // k == 0 or alpha == 0: C <- beta*C
     std::vector<IJob> singles; // longer than one int32 pass: run alone
     int64_t off_sj = 0, off_ij = 0, off_fj = 0;

@@ -63,6 +63,7 @@ struct I8Tile {
     int KS;     // K bytes per LDS stage (32 or 64)
     int GM;     // tile rows per group of the tile order (L2 reuse)
     int pipe;   // next stage's fragments read while the current one computes
+    int occ;    // workgroups per CU (each gets 1/occ of the LDS ring space)
     int bm() const { return WGM * 32 * TM; }
     int bn() const { return WGN * 32 * TN; }
     int threads() const { return 64 * WGM * WGN; }
@@ -71,6 +72,8 @@ struct I8Tile {
 int i8_tile_count();
 const I8Tile &i8_tile(int id);
 int i8_default_tile(int S);
+// Default for persistent batched launches.
+int i8_batch_tile(int S);
 // Tile chosen by the autotuner for this slice count and size, or -1.
 int tuned_i8_tile(int S, int64_t m, int64_t n, int64_t k);
 constexpr int I8_BK = 64;
@@ -224,9 +227,11 @@ hipError_t launch_i8(int tile, const I8Job &job, hipStream_t st);
 // workgroup per tile, no persistent queue.
 hipError_t launch_i8_jobs(int tile, const I8Job *dev_jobs, int njobs, int total_tiles,
                           hipStream_t st);
+// uniform_s: every job has the tile's digit count, so the tile loop is
+// compiled for that count alone (no dispatch over digit counts).
 hipError_t launch_i8_batched(int tile, const I8Job *dev_jobs, int njobs,
                              int total_tiles, int persistent, unsigned *ctr,
-                             hipStream_t st);
+                             hipStream_t st, bool uniform_s = false);
 
 // Triangular solve (kernels_trsm.hip): the block recursion stops at leaves
 // of at most TRSM_LEAF_MAX rows (a multiple of 64), solved by one kernel.

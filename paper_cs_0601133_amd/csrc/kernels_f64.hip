@@ -292,7 +292,7 @@ void k_fgemm_f64_batched(const F64Job *__restrict__ jobs, int njobs, int total, 
         if (persistent) {
             if (threadIdx.x == 0) s_tile = (int)atomicAdd(&ctr[0], 1u);
             __syncthreads();
-            g = s_tile;
+            g = __builtin_amdgcn_readfirstlane(s_tile); // uniform: job fields stay scalar
             __syncthreads();
         }
         if (g >= total) break;

@@ -53,12 +53,13 @@ struct Cfg {
     static constexpr int H = KS / 32; // 32-deep matrix-core steps per stage
 };
 
-// Stages in the LDS ring: as many as fit (at most 6, at least 2); NST - 1
-// stages are in flight while one is consumed.
-template <int S, int TM, int TN, int WGM, int WGN, int KS>
+// Stages in the LDS ring: as many as fit in the CU's LDS share of one of
+// OCC resident workgroups (at most 6, at least 2); NST - 1 stages are in
+// flight while one is consumed.
+template <int S, int TM, int TN, int WGM, int WGN, int KS, int OCC>
 struct Ring {
     static constexpr int STAGE = Cfg<S, TM, TN, WGM, WGN, KS>::STAGE;
-    static constexpr int FIT = LDS_LIMIT / STAGE;
+    static constexpr int FIT = (LDS_LIMIT / OCC - (OCC > 1 ? 512 : 0)) / STAGE;
     static constexpr int NST = FIT > 6 ? 6 : (FIT < 2 ? 2 : FIT);
     static constexpr int BYTES = NST * STAGE;
 };
@@ -309,18 +310,19 @@ __device__ __forceinline__ void i8_tile(const I8Job &J, int tm, int tn, char *sm
             }
 }
 
-// Waves per SIMD implied by the workgroup size (one workgroup per CU).
-template <int WGM, int WGN>
+// Waves per SIMD implied by the workgroup size and the number of resident
+// workgroups per CU.
+template <int WGM, int WGN, int OCC>
 struct Wpe {
-    static constexpr int v = (WGM * WGN) / 4 > 0 ? (WGM * WGN) / 4 : 1;
+    static constexpr int v = (WGM * WGN * OCC) / 4 > 0 ? (WGM * WGN * OCC) / 4 : 1;
 };
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE, int OCC>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
-                          amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
+                          amdgpu_waves_per_eu(Wpe<WGM, WGN, OCC>::v, Wpe<WGM, WGN, OCC>::v)))
 void k_fgemm_i8(I8Job J)
 {
-    using R = Ring<S, TM, TN, WGM, WGN, KS>;
+    using R = Ring<S, TM, TN, WGM, WGN, KS, OCC>;
     __shared__ __attribute__((aligned(1024))) char smem[R::BYTES];
     const int G = J.tiles_m * J.tiles_n;
     const int t = xcd_remap(blockIdx.x, G);
@@ -344,13 +346,14 @@ __device__ __forceinline__ void i8_tile_any(const I8Job &J, int tm, int tn, char
     if constexpr (S > 1) i8_tile_any<S - 1, TM, TN, WGM, WGN, KS, NST, PIPE>(J, tm, tn, smem);
 }
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
+// UNI: every job has S digits; only the S-digit tile body is compiled.
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE, int OCC, bool UNI>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
-                          amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
+                          amdgpu_waves_per_eu(Wpe<WGM, WGN, OCC>::v, Wpe<WGM, WGN, OCC>::v)))
 void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
                         int persistent, unsigned *ctr)
 {
-    using R = Ring<S, TM, TN, WGM, WGN, KS>;
+    using R = Ring<S, TM, TN, WGM, WGN, KS, OCC>;
     __shared__ __attribute__((aligned(1024))) char smem[R::BYTES];
     __shared__ int s_tile;
     int g = persistent ? 0 : (int)blockIdx.x;
@@ -358,7 +361,7 @@ void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
         if (persistent) {
             if (threadIdx.x == 0) s_tile = (int)atomicAdd(&ctr[0], 1u);
             __syncthreads();
-            g = s_tile;
+            g = __builtin_amdgcn_readfirstlane(s_tile); // uniform: job fields stay scalar
             __syncthreads();
         }
         if (g >= total) break;
@@ -370,7 +373,10 @@ void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
         const I8Job J = jobs[lo];
         int tm, tn;
         grouped_tile_rt(g - J.tile_start, J.tiles_m, J.tiles_n, J.gm, &tm, &tn);
-        i8_tile_any<S, TM, TN, WGM, WGN, KS, R::NST, PIPE>(J, tm, tn, smem);
+        if constexpr (UNI)
+            i8_tile<S, TM, TN, WGM, WGN, KS, R::NST, PIPE>(J, tm, tn, smem);
+        else
+            i8_tile_any<S, TM, TN, WGM, WGN, KS, R::NST, PIPE>(J, tm, tn, smem);
         if (!persistent) break;
     }
     if (persistent && threadIdx.x == 0) {
@@ -387,12 +393,12 @@ void k_fgemm_i8_batched(const I8Job *__restrict__ jobs, int njobs, int total,
 // rows): one workgroup per tile, tiles renumbered so that neighbours in a
 // job's tile order share an XCD, and only the S-digit tile body compiled
 // (the general table kernel's dispatch over digit counts costs registers).
-template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE, int OCC>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WGM * WGN, 64 * WGM * WGN),
-                          amdgpu_waves_per_eu(Wpe<WGM, WGN>::v, Wpe<WGM, WGN>::v)))
+                          amdgpu_waves_per_eu(Wpe<WGM, WGN, OCC>::v, Wpe<WGM, WGN, OCC>::v)))
 void k_fgemm_i8_jobs(const I8Job *__restrict__ jobs, int njobs, int total)
 {
-    using R = Ring<S, TM, TN, WGM, WGN, KS>;
+    using R = Ring<S, TM, TN, WGM, WGN, KS, OCC>;
     __shared__ __attribute__((aligned(1024))) char smem[R::BYTES];
     const int g = xcd_remap((int)blockIdx.x, total);
     int lo = 0, hi = njobs - 1;
@@ -406,88 +412,103 @@ void k_fgemm_i8_jobs(const I8Job *__restrict__ jobs, int njobs, int total)
     i8_tile<S, TM, TN, WGM, WGN, KS, R::NST, PIPE>(J, tm, tn, smem);
 }
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE, int OCC>
 hipError_t run_jobs(const I8Job *jobs, int njobs, int total, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fgemm_i8_jobs<S, TM, TN, WGM, WGN, KS, PIPE>), dim3(total),
+    hipLaunchKernelGGL((k_fgemm_i8_jobs<S, TM, TN, WGM, WGN, KS, PIPE, OCC>), dim3(total),
                        dim3(64 * WGM * WGN), 0, st, jobs, njobs, total);
     return hipGetLastError();
 }
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE, int OCC>
 hipError_t run_single(const I8Job &J, hipStream_t st)
 {
     const int G = J.tiles_m * J.tiles_n;
-    hipLaunchKernelGGL((k_fgemm_i8<S, TM, TN, WGM, WGN, KS, PIPE>), dim3(G),
+    hipLaunchKernelGGL((k_fgemm_i8<S, TM, TN, WGM, WGN, KS, PIPE, OCC>), dim3(G),
                        dim3(64 * WGM * WGN), 0, st, J);
     return hipGetLastError();
 }
 
-template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE>
+template <int S, int TM, int TN, int WGM, int WGN, int KS, bool PIPE, int OCC>
 hipError_t run_batched(const I8Job *jobs, int njobs, int total, int persistent,
-                       unsigned *ctr, hipStream_t st)
+                       unsigned *ctr, hipStream_t st, bool uniform)
 {
     int grid = total;
     if (persistent) {
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        cus *= OCC; // resident workgroups
         grid = cus < total ? cus : total;
         if (grid < 1) grid = 1;
     }
-    hipLaunchKernelGGL((k_fgemm_i8_batched<S, TM, TN, WGM, WGN, KS, PIPE>), dim3(grid),
-                       dim3(64 * WGM * WGN), 0, st, jobs, njobs, total, persistent, ctr);
+    if (uniform)
+        hipLaunchKernelGGL((k_fgemm_i8_batched<S, TM, TN, WGM, WGN, KS, PIPE, OCC, true>),
+                           dim3(grid), dim3(64 * WGM * WGN), 0, st, jobs, njobs, total,
+                           persistent, ctr);
+    else
+        hipLaunchKernelGGL((k_fgemm_i8_batched<S, TM, TN, WGM, WGN, KS, PIPE, OCC, false>),
+                           dim3(grid), dim3(64 * WGM * WGN), 0, st, jobs, njobs, total,
+                           persistent, ctr);
     return hipGetLastError();
 }
 
 } // namespace
 
-// Compiled configurations: id, S, TM, TN, WGM, WGN, KS, GM, PIPE.  Each
+// Compiled configurations: id, S, TM, TN, WGM, WGN, KS, GM, PIPE, OCC.  Each
 // (WGM x WGN) workgroup of 64-lane waves owns a (WGM*32*TM) x (WGN*32*TN)
 // tile of C; 2S-1 accumulator sets of TM*TN 32x32 blocks live in each wave;
 // KS bytes of K per LDS stage; GM tile rows per group of the tile order;
-// PIPE: fragment reads of the next stage overlap the current stage.
+// PIPE: fragment reads of the next stage overlap the current stage; OCC
+// workgroups share a CU (their phases drift apart, so one workgroup's
+// epilogue and stage barriers overlap the other's matrix-core work).
 #define FF_I8_TILES(X)                                                            \
-    X(0, 1, 2, 2, 2, 2, 64, 8, 0)  /* 128 x 128, 4 waves,   64 acc */             \
-    X(1, 1, 2, 2, 4, 2, 64, 8, 0)  /* 256 x 128, 8 waves,   64 acc */             \
-    X(2, 1, 2, 2, 4, 2, 32, 8, 0)  /* 256 x 128, 8 waves, half stages */          \
-    X(3, 2, 1, 2, 4, 2, 32, 8, 0)  /* 128 x 128, 8 waves,   96 acc, half stages */\
-    X(4, 2, 1, 2, 4, 2, 64, 8, 0)  /* 128 x 128, 8 waves,   96 acc */             \
-    X(5, 3, 1, 2, 4, 2, 32, 8, 0)  /* 128 x 128, 8 waves,  160 acc, half stages */\
-    X(6, 3, 1, 2, 4, 2, 64, 8, 0)  /* 128 x 128, 8 waves,  160 acc */             \
-    X(7, 3, 1, 1, 4, 2, 64, 8, 0)  /* 128 x  64, 8 waves,   80 acc */             \
-    X(8, 4, 1, 1, 4, 2, 64, 8, 0)  /* 128 x  64, 8 waves,  112 acc */             \
-    X(9, 4, 1, 1, 4, 2, 64, 4, 0)  /* 128 x  64, 8 waves,  groups of 4 */         \
-    X(10, 4, 1, 1, 2, 4, 64, 8, 0) /*  64 x 128, 8 waves,  112 acc */             \
-    X(11, 4, 1, 1, 4, 2, 32, 4, 0) /* 128 x  64, half stages, groups of 4 */      \
-    X(12, 5, 1, 1, 4, 2, 64, 8, 0) /* 128 x  64, 8 waves,  144 acc */             \
-    X(13, 4, 1, 1, 4, 2, 32, 8, 0) /* 128 x  64, half stages */                   \
-    X(14, 4, 1, 1, 4, 2, 32, 8, 1) /* 128 x  64, half stages, pipelined */        \
-    X(15, 4, 1, 1, 4, 2, 64, 8, 1) /* 128 x  64, pipelined */                     \
-    X(16, 3, 1, 2, 4, 2, 32, 8, 1) /* 128 x 128, half stages, pipelined */        \
-    X(17, 1, 2, 2, 4, 2, 32, 8, 1) /* 256 x 128, half stages, pipelined */        \
-    X(18, 2, 1, 2, 4, 2, 32, 8, 1) /* 128 x 128, half stages, pipelined */        \
-    X(19, 1, 2, 4, 4, 2, 64, 8, 0) /* 256 x 256, 8 waves,  128 acc */
+    X(0, 1, 2, 2, 2, 2, 64, 8, 0, 1)  /* 128 x 128, 4 waves,   64 acc */             \
+    X(1, 1, 2, 2, 4, 2, 64, 8, 0, 1)  /* 256 x 128, 8 waves,   64 acc */             \
+    X(2, 1, 2, 2, 4, 2, 32, 8, 0, 1)  /* 256 x 128, 8 waves, half stages */          \
+    X(3, 2, 1, 2, 4, 2, 32, 8, 0, 1)  /* 128 x 128, 8 waves,   96 acc, half stages */\
+    X(4, 2, 1, 2, 4, 2, 64, 8, 0, 1)  /* 128 x 128, 8 waves,   96 acc */             \
+    X(5, 3, 1, 2, 4, 2, 32, 8, 0, 1)  /* 128 x 128, 8 waves,  160 acc, half stages */\
+    X(6, 3, 1, 2, 4, 2, 64, 8, 0, 1)  /* 128 x 128, 8 waves,  160 acc */             \
+    X(7, 3, 1, 1, 4, 2, 64, 8, 0, 1)  /* 128 x  64, 8 waves,   80 acc */             \
+    X(8, 4, 1, 1, 4, 2, 64, 8, 0, 1)  /* 128 x  64, 8 waves,  112 acc */             \
+    X(9, 4, 1, 1, 4, 2, 64, 4, 0, 1)  /* 128 x  64, 8 waves,  groups of 4 */         \
+    X(10, 4, 1, 1, 2, 4, 64, 8, 0, 1) /*  64 x 128, 8 waves,  112 acc */             \
+    X(11, 4, 1, 1, 4, 2, 32, 4, 0, 1) /* 128 x  64, half stages, groups of 4 */      \
+    X(12, 5, 1, 1, 4, 2, 64, 8, 0, 1) /* 128 x  64, 8 waves,  144 acc */             \
+    X(13, 4, 1, 1, 4, 2, 32, 8, 0, 1) /* 128 x  64, half stages */                   \
+    X(14, 4, 1, 1, 4, 2, 32, 8, 1, 1) /* 128 x  64, half stages, pipelined */        \
+    X(15, 4, 1, 1, 4, 2, 64, 8, 1, 1) /* 128 x  64, pipelined */                     \
+    X(16, 3, 1, 2, 4, 2, 32, 8, 1, 1) /* 128 x 128, half stages, pipelined */        \
+    X(17, 1, 2, 2, 4, 2, 32, 8, 1, 1) /* 256 x 128, half stages, pipelined */        \
+    X(18, 2, 1, 2, 4, 2, 32, 8, 1, 1) /* 128 x 128, half stages, pipelined */        \
+    X(19, 1, 2, 4, 4, 2, 64, 8, 0, 1) /* 256 x 256, 8 waves,  128 acc */             \
+    X(20, 1, 2, 2, 2, 2, 64, 4, 1, 2) /* 128 x 128, 4 waves, 2 per CU, pipelined */
 
 namespace {
 const I8Tile k_tiles[] = {
-#define FF_ROW(id, S, TM, TN, WGM, WGN, KS, GM, PIPE) I8Tile{id, S, TM, TN, WGM, WGN, KS, GM, PIPE},
+#define FF_ROW(id, S, TM, TN, WGM, WGN, KS, GM, PIPE, OCC) \
+    I8Tile{id, S, TM, TN, WGM, WGN, KS, GM, PIPE, OCC},
     FF_I8_TILES(FF_ROW)
 #undef FF_ROW
 };
-// Default configuration per slice count (index = S).
-const int k_default[6] = {-1, 19, 4, 6, 15, 12};
+// Default configuration per slice count (index = S), for single products
+// and for persistent batches (whose tile loop must also hold the job
+// table's fields: configurations that stay within 256 VGPRs there).
+const int k_default[6] = {-1, 20, 4, 6, 15, 12};
+const int k_batch_default[6] = {-1, 20, 18, 16, 15, 12};
 } // namespace
 
 int i8_tile_count() { return (int)(sizeof(k_tiles) / sizeof(k_tiles[0])); }
 const I8Tile &i8_tile(int id) { return k_tiles[id]; }
 int i8_default_tile(int S) { return (S >= 1 && S <= 5) ? k_default[S] : -1; }
+int i8_batch_tile(int S) { return (S >= 1 && S <= 5) ? k_batch_default[S] : -1; }
 
 hipError_t launch_i8(int tile, const I8Job &J, hipStream_t st)
 {
     switch (tile) {
-#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE)                              \
-    case id: return run_single<S, TM, TN, WGM, WGN, KS, PIPE>(J, st);
+#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE, OCC)                         \
+    case id: return run_single<S, TM, TN, WGM, WGN, KS, PIPE, OCC>(J, st);
         FF_I8_TILES(FF_CASE)
 #undef FF_CASE
     default: return hipErrorInvalidValue;
@@ -498,8 +519,8 @@ hipError_t launch_i8_jobs(int tile, const I8Job *jobs, int njobs, int total, hip
 {
     if (total <= 0) return hipSuccess;
     switch (tile) {
-#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE)                              \
-    case id: return run_jobs<S, TM, TN, WGM, WGN, KS, PIPE>(jobs, njobs, total, st);
+#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE, OCC)                         \
+    case id: return run_jobs<S, TM, TN, WGM, WGN, KS, PIPE, OCC>(jobs, njobs, total, st);
         FF_I8_TILES(FF_CASE)
 #undef FF_CASE
     default: return hipErrorInvalidValue;
@@ -507,12 +528,13 @@ hipError_t launch_i8_jobs(int tile, const I8Job *jobs, int njobs, int total, hip
 }
 
 hipError_t launch_i8_batched(int tile, const I8Job *jobs, int njobs, int total,
-                             int persistent, unsigned *ctr, hipStream_t st)
+                             int persistent, unsigned *ctr, hipStream_t st, bool uniform_s)
 {
     switch (tile) {
-#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE)                              \
+#define FF_CASE(id, S, TM, TN, WGM, WGN, KS, GM, PIPE, OCC)                         \
     case id:                                                                          \
-        return run_batched<S, TM, TN, WGM, WGN, KS, PIPE>(jobs, njobs, total, persistent, ctr, st);
+        return run_batched<S, TM, TN, WGM, WGN, KS, PIPE, OCC>(jobs, njobs, total, persistent, ctr, \
+                                                              st, uniform_s);
         FF_I8_TILES(FF_CASE)
 #undef FF_CASE
     default: return hipErrorInvalidValue;

@@ -180,3 +180,50 @@ def test_multimodular_full_size_crt(path):
             r2, c2 = rng.integers(0, n, 64), rng.integers(0, n, 64)
             want = oracle.fgemm_entries(p, Ap, Bp, r2, c2)
             assert np.array_equal(got[r2, c2], want), (n, p)
+
+
+def test_multimodular_full_size_graph_replays():
+    # The 64-job configuration as one captured persistent launch, replayed
+    # three times with eager work in between: after every replay, Chinese
+    # remaindering of 4 primes per size on sampled entries against the exact
+    # integer product, sampled entries of every job, and (first replay) the
+    # whole output of one job per size against the oracle.
+    import torch
+    A, B, jobs = multimodular(2048, [512, 1024, 1536, 2048], 64, 43)
+    dev, abi, keep = [], [], []
+    for (p, n) in jobs:
+        Ap, Bp = reduce_mod(A[:n, :n], p), reduce_mod(B[:n, :n], p)
+        dA, dB = to_dev(Ap), to_dev(Bp)
+        dC = to_dev(np.zeros((n, n), np.uint32))
+        keep.append((dA, dB))
+        dev.append((p, n, Ap, Bp, dC))
+        abi.append(ff.job(p, dA, dB, dC))
+    torch.cuda.synchronize()
+    g = ff.ff_batch_graph_create(abi, ff.make_opts(path=ff.FF_PATH_INT8))
+    rng = np.random.default_rng(8)
+    try:
+        stream = torch.cuda.current_stream()
+        for replay in range(3):
+            for (_, _, _, _, dC) in dev:
+                dC.fill_(-1)
+            torch.cuda.synchronize()
+            ff.ff_batch_graph_launch(g, stream.cuda_stream)
+            torch.cuda.synchronize()
+            by_size = {}
+            for (p, n, Ap, Bp, dC) in dev:
+                by_size.setdefault(n, []).append((p, Ap, Bp, from_dev(dC)))
+            for n, lst in by_size.items():
+                rows, cols = rng.integers(0, n, 16), rng.integers(0, n, 16)
+                elo, ehi = oracle.int_matmul(A[rows, :n], B[:n, cols])
+                lo, hi = oracle.crt([q for q, _, _, _ in lst[:4]],
+                                    [got[np.ix_(rows, cols)] for _, _, _, got in lst[:4]])
+                assert np.array_equal(lo, elo) and np.array_equal(hi, ehi), (replay, n)
+                for p, Ap, Bp, got in lst:
+                    r2, c2 = rng.integers(0, n, 32), rng.integers(0, n, 32)
+                    assert np.array_equal(got[r2, c2], oracle.fgemm_entries(p, Ap, Bp, r2, c2)), \
+                        (replay, n, p)
+                if replay == 0:
+                    p, Ap, Bp, got = lst[0]
+                    assert np.array_equal(got, oracle.fgemm(p, Ap, Bp)), (n, p)
+    finally:
+        ff.ff_batch_graph_destroy(g)
