@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--settle-s", type=float, default=0.3,
+                    help="untimed calls of each timed workload for this long before its "
+                         "warm-up steps: the GPU's clocks take tens of ms of sustained "
+                         "matrix-core load to settle")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -80,12 +84,32 @@ def gops(ops, ms):
     return ops / ms / 1e6
 
 
+SETTLE_S = 0.3
+
+
+def settle(torch, fn, seconds=None):
+    """Untimed calls for about `seconds` of wall time (the clock controller
+    needs tens of ms of sustained load to reach its steady state)."""
+    seconds = SETTLE_S if seconds is None else seconds
+    t0 = time.perf_counter()
+    calls = 0
+    while time.perf_counter() - t0 < seconds:
+        fn()
+        calls += 1
+        if calls % 8 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return calls
+
+
 def time_calls(torch, fn, steps, warmup, ff=None):
     """Per-call event timing on torch's stream; returns (mean ms, per-call
     ms, profile of the library's kernels).  The timed calls bracket only the
     matrix-core kernel with HIP events (its duration gives the roofline); the
     operand passes (slicing, packing) are timed on a few extra calls after
-    the timed region, so that their events do not lengthen the timed steps."""
+    the timed region, so that their events do not lengthen the timed steps.
+    Before the warm-up steps, untimed calls run for SETTLE_S seconds."""
+    settle(torch, fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -123,8 +147,9 @@ def residues_dev(torch, shape, p, seed):
     return torch.from_numpy(a.view(np.int32)).cuda(), a
 
 
-def cpu_baseline(A, B, C, seconds):
-    """The oracle on a bounded sample: full rows of C = 3AB + 5C mod p."""
+def cpu_baseline(A, B, C, seconds, gpu_rows=None):
+    """The oracle on a bounded sample: full rows of C = 3AB + 5C mod p.  The
+    rows are also compared with the same rows of one GPU call (gpu_rows)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     os.environ.setdefault("OMP_NUM_THREADS", str(threads))
@@ -136,10 +161,11 @@ def cpu_baseline(A, B, C, seconds):
     dt = max(time.perf_counter() - t, 1e-3)
     rows = int(max(probe, min(M, probe * max(1, round(seconds / dt)))))
     t = time.perf_counter()
-    oracle.fgemm(P, A[:rows], B, C[:rows], ALPHA, BETA)
+    want = oracle.fgemm(P, A[:rows], B, C[:rows], ALPHA, BETA)
     dt = time.perf_counter() - t
+    match = None if gpu_rows is None else bool(np.array_equal(want, gpu_rows[:rows]))
     return {"value": 2.0 * rows * N * K / dt / 1e9, "unit": "Gop/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "rows_equal_to_gpu": match,
             "sample": f"{rows} full rows of the 4096 x 4096 x 4096 product mod 8388593 "
                       f"({rows * N * K:.3g} multiply-adds, {dt:.1f} s), scaled to Gop/s"}
 
@@ -168,21 +194,52 @@ def measured_traffic():
         return None
 
 
+def freivalds_check(A, B, C0, Cout, alpha, beta, p, trials, seed):
+    """Cout == alpha*A*B + beta*C0 (mod p)?  Freivalds' test with `trials`
+    random vectors (false acceptance <= p^-trials), in exact uint64 numpy
+    arithmetic: every product below is < 2^58."""
+    rng = np.random.default_rng(seed)
+    A64, B64 = A.astype(np.uint64), B.astype(np.uint64)
+    C064, Co64 = C0.astype(np.uint64), Cout.astype(np.uint64)
+    P64 = np.uint64(p)
+    for _ in range(trials):
+        x = rng.integers(0, p, B.shape[1], dtype=np.uint64)
+        bx = (B64 @ x) % P64
+        abx = (A64 @ bx) % P64
+        want = (np.uint64(alpha) * abx % P64 + np.uint64(beta) * ((C064 @ x) % P64) % P64) % P64
+        if not np.array_equal((Co64 @ x) % P64, want):
+            return False
+    return True
+
+
+def repeated_coeffs(calls, alpha, beta, p):
+    """After `calls` applications of C <- alpha*A*B + beta*C to C0:
+    C = alpha*(1 + beta + ... + beta^(calls-1))*A*B + beta^calls*C0 (mod p)."""
+    geo, bpow = 0, 1
+    for _ in range(calls):
+        geo = (geo + bpow) % p
+        bpow = bpow * beta % p
+    return alpha * geo % p, bpow
+
+
 def headline(torch, ff, args):
     dA, A = residues_dev(torch, (M, K), P, 0x5EED0000 + 2000 + 1)
     dB, B = residues_dev(torch, (K, N), P, 0x5EED0000 + 2000 + 2)
     dC, C = residues_dev(torch, (M, N), P, 0x5EED0000 + 2000 + 3)
     ops = 2.0 * M * N * K
     res = {}
+    calls = [0]   # every call below applies C <- 3AB + 5C to the same dC
     for name, opts in (("int8_d7", ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7,
                                                  winograd_levels=0)),
                        ("int8_d8", ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=8,
                                                  winograd_levels=0)),
                        ("fp64", ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0))):
         info = ff.ff_plan_query(P, 0, 0, M, N, K, opts)
-        ms, per, prof = time_calls(
-            torch, lambda: ff.fgemm(P, dA, dB, dC, ALPHA, BETA, opts=opts),
-            args.steps, args.warmup, ff)
+
+        def step(opts=opts):
+            ff.fgemm(P, dA, dB, dC, ALPHA, BETA, opts=opts)
+            calls[0] += 1
+        ms, per, prof = time_calls(torch, step, args.steps, args.warmup, ff)
         gemm_ms = prof["gemm_ms"] / max(prof["gemm_launches"], 1)
         slice_ms = prof["slice_ms"] / max(prof["slice_launches"], 1)
         r = {"ms_per_step": ms, "gops": gops(ops, ms), **summarize(per),
@@ -201,12 +258,30 @@ def headline(torch, ff, args):
     # the same product with one Winograd level (seven half-size digit
     # products, Section 3.2), beside the plain path: effective 2mnk/t
     o = ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7, winograd_levels=1)
-    ms, per, _ = time_calls(torch, lambda: ff.fgemm(P, dA, dB, dC, ALPHA, BETA, opts=o),
-                            args.steps, args.warmup)
+
+    def wstep():
+        ff.fgemm(P, dA, dB, dC, ALPHA, BETA, opts=o)
+        calls[0] += 1
+    ms, per, _ = time_calls(torch, wstep, args.steps, args.warmup)
     res["int8_d7_winograd1"] = {"ms_per_step": ms, "gops_effective": gops(ops, ms),
                                 **summarize(per)}
     log(f"4096 int8_d7_winograd1: {ms:.3f} ms/step, {gops(ops, ms):.0f} Gop/s (2mnk/t)")
-    return res, (A, B, C)
+    # The timed output itself: after `calls` applications on the same C, by
+    # Freivalds against the closed form of the repeated update.
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy().view(np.uint32)
+    a_T, b_T = repeated_coeffs(calls[0], ALPHA, BETA, P)
+    ok = freivalds_check(A, B, C, out, a_T, b_T, P, 2, 77)
+    res["check"] = {"kind": "freivalds", "trials": 2, "calls_applied": calls[0], "ok": bool(ok)}
+    log(f"4096 timed output after {calls[0]} calls: Freivalds {'ok' if ok else 'FAILED'}")
+    # one call from C0 on the headline path: rows the CPU leg compares with
+    # the oracle
+    dC.copy_(torch.from_numpy(C.view(np.int32)).cuda())
+    ff.fgemm(P, dA, dB, dC, ALPHA, BETA,
+             opts=ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7, winograd_levels=0))
+    torch.cuda.synchronize()
+    one_call = dC.cpu().numpy().view(np.uint32).copy()
+    return res, (A, B, C, one_call)
 
 
 def small_latency(torch, ff, args):
@@ -430,7 +505,7 @@ def serving(torch, ff, args):
         dA = torch.randint(0, p, (m, k), dtype=torch.int32, device="cuda", generator=g)
         dB = torch.randint(0, p, (k, n), dtype=torch.int32, device="cuda", generator=g)
         dC = torch.randint(0, p, (m, n), dtype=torch.int32, device="cuda", generator=g)
-        reqs.append((ff.job(p, dA, dB, dC, 3, 5), (dA, dB, dC), 2.0 * m * n * k))
+        reqs.append((ff.job(p, dA, dB, dC, 3, 5), (dA, dB, dC, dC.clone(), p), 2.0 * m * n * k))
     torch.cuda.synchronize()
     total_ops = sum(r[2] for r in reqs)
     budget = 24 << 30
@@ -468,6 +543,16 @@ def serving(torch, ff, args):
                                   "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                                   "max_inflight": st["max_inflight"]}
         log(f"serve poisson {load}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms")
+    # every request's result after the three runs (C <- 3AB + 5C applied
+    # three times), by Freivalds against its initial C
+    torch.cuda.synchronize()
+    good = 0
+    for i, (_, (dA, dB, dC, dC0, p), _) in enumerate(reqs):
+        a_T, b_T = repeated_coeffs(3, 3, 5, p)
+        host = [t.cpu().numpy().view(np.uint32) for t in (dA, dB, dC0, dC)]
+        good += freivalds_check(host[0], host[1], host[2], host[3], a_T, b_T, p, 1, 1000 + i)
+    out["check"] = {"kind": "freivalds", "trials": 1, "requests": nreq, "ok": int(good)}
+    log(f"serve: {good} of {nreq} results pass Freivalds")
     return out
 
 
@@ -496,7 +581,10 @@ def main():
     if args.latency_only:
         print(json.dumps({"workloads": {"n256_p65521_latency": small_latency(torch, ff, args)}}))
         return
-    paths, (A, B, C) = headline(torch, ff, args)
+    global SETTLE_S
+    SETTLE_S = args.settle_s
+    paths, (A, B, C, one_call) = headline(torch, ff, args)
+    check = paths.pop("check")
     head = paths["int8_d7"]
     ops = 2.0 * M * N * K
     line = {
@@ -506,6 +594,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_s": args.settle_s,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -522,6 +611,7 @@ def main():
                      "frac": head["frac_int8_peak"], "traffic": measured_traffic(),
                      "kernel": "k_fgemm_i8 (S=4)", "ops_per_launch": 16 * ops},
         "paths": paths,
+        "check": check,
         "int8_vs_fp64_speedup": paths["fp64"]["ms_per_step"] / head["ms_per_step"],
     }
     if args.headline_only:
@@ -543,7 +633,7 @@ def main():
             "serving": serving(torch, ff, args),
         }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(A, B, C, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(A, B, C, args.cpu_seconds, one_call)
     print(json.dumps(line))
 
 
