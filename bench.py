@@ -73,6 +73,10 @@ def parse():
                     help="time only the 8192^3 products with 0-2 Winograd levels (profiler runs)")
     ap.add_argument("--latency-only", action="store_true",
                     help="time only the 256^3 latency workload (profiler runs)")
+    ap.add_argument("--multimodular-only", action="store_true",
+                    help="time only the 64-job multi-modular batch (profiler runs)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the Poisson serving stream (profiler runs)")
     return ap.parse_args()
 
 
@@ -580,6 +584,12 @@ def main():
         return
     if args.latency_only:
         print(json.dumps({"workloads": {"n256_p65521_latency": small_latency(torch, ff, args)}}))
+        return
+    if args.multimodular_only:
+        print(json.dumps({"workloads": {"multimodular_64_jobs": multimodular(torch, ff, args)}}))
+        return
+    if args.serving_only:
+        print(json.dumps({"workloads": {"serving": serving(torch, ff, args)}}))
         return
     global SETTLE_S
     SETTLE_S = args.settle_s
