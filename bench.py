@@ -237,7 +237,9 @@ def headline(torch, ff, args):
                                                  winograd_levels=0)),
                        ("int8_d8", ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=8,
                                                  winograd_levels=0)),
-                       ("fp64", ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0))):
+                       ("fp64", ff.make_opts(path=ff.FF_PATH_FP64, winograd_levels=0)),
+                       ("int8_d7_pairing", ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7,
+                                                         winograd_levels=0, digit_pairing=1))):
         info = ff.ff_plan_query(P, 0, 0, M, N, K, opts)
 
         def step(opts=opts):
@@ -249,9 +251,9 @@ def headline(torch, ff, args):
         r = {"ms_per_step": ms, "gops": gops(ops, ms), **summarize(per),
              "gemm_kernel_ms": gemm_ms, "slice_kernel_ms": slice_ms,
              "slices": info.slices, "digit_bits": info.digit_bits, "kblock": info.kblock,
-             "tile_config": info.tile_config}
+             "tile_config": info.tile_config, "digit_products": info.digit_products}
         if info.path == ff.FF_PATH_INT8:
-            r["mfma_tops"] = info.slices ** 2 * ops / gemm_ms / 1e9
+            r["mfma_tops"] = info.digit_products * ops / gemm_ms / 1e9
             r["frac_int8_peak"] = r["mfma_tops"] / PEAK_INT8_TOPS
         else:
             r["mfma_tflops"] = ops / gemm_ms / 1e9
@@ -286,6 +288,33 @@ def headline(torch, ff, args):
     torch.cuda.synchronize()
     one_call = dC.cpu().numpy().view(np.uint32).copy()
     return res, (A, B, C, one_call)
+
+
+def large_modulus(torch, ff, args):
+    """4096^3 at p = 2^31 - 1: 8-bit digits (4 slices, 16 products), 7-bit
+    digits (5 slices, 25 products) and 7-bit digits with pairing (5 slices,
+    15 products of digits and digit sums)."""
+    p, n = 2147483647, 4096
+    ops = 2.0 * n ** 3
+    dA, _ = residues_dev(torch, (n, n), p, 0x5EED0000 + 2500 + 1)
+    dB, _ = residues_dev(torch, (n, n), p, 0x5EED0000 + 2500 + 2)
+    dC = torch.zeros((n, n), dtype=torch.int32, device="cuda")
+    out = {}
+    for name, opts in (("int8_d8", ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=8,
+                                                 winograd_levels=0)),
+                       ("int8_d7", ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7,
+                                                 winograd_levels=0)),
+                       ("int8_d7_pairing", ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7,
+                                                         winograd_levels=0, digit_pairing=1))):
+        info = ff.ff_plan_query(p, 0, 0, n, n, n, opts)
+        ms, per, prof = time_calls(torch, lambda: ff.fgemm(p, dA, dB, dC, 1, 0, opts=opts),
+                                   5, 1, ff)
+        g = prof["gemm_ms"] / max(1, prof["gemm_launches"])
+        out[name] = {"ms": ms, "gops": gops(ops, ms), "gemm_kernel_ms": g,
+                     "slices": info.slices, "digit_products": info.digit_products,
+                     "frac_int8_peak": info.digit_products * ops / g / 1e9 / PEAK_INT8_TOPS}
+        log(f"4096 p=2^31-1 {name}: {ms:.3f} ms ({info.digit_products} digit products)")
+    return out
 
 
 def small_latency(torch, ff, args):
@@ -635,6 +664,7 @@ def main():
     if not args.headline_only:
         line["workloads"] = {
             "n256_p65521_latency": small_latency(torch, ff, args),
+            "n4096_p2147483647": large_modulus(torch, ff, args),
             "n8192": large_8192(torch, ff, args),
             "multimodular_64_jobs": multimodular(torch, ff, args),
             "ftrsm": triangular_solve(torch, ff, args),

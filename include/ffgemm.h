@@ -108,6 +108,14 @@ typedef struct ff_opts {
                             unreduced integers, the form Theorem 3.1 bounds); 2
                             reduced to centered residues at the leaves             */
     void *stream;        /* hipStream_t to enqueue on; NULL: the ff_set_stream one */
+    int digit_pairing;   /* INT8 path with 7-bit digits, plain products (no
+                            Winograd level; automatic levels become none): the
+                            cross terms a_i b_j + a_j b_i come from one product
+                            of digit sums, (a_i + a_j)(b_i + b_j) - a_i b_i
+                            - a_j b_j (Karatsuba's identity per pair of digits;
+                            sums of two 7-bit digits fit int8), so S(S+1)/2
+                            digit products replace S^2 at the cost of S(S+1)/2
+                            planes per operand instead of S.  0: off           */
 } ff_opts;
 
 /* What a call will do (ff_plan_query).  Host-only; no device is touched. */
@@ -123,7 +131,10 @@ typedef struct ff_plan_info {
     int64_t kblock;          /* FP64: products summed between two reductions;
                                 INT8: largest K of one exact int32 pass             */
     int64_t workspace_bytes; /* device workspace the call needs                     */
-    int tile_config;         /* kernel tile configuration id                        */
+    int tile_config;         /* kernel tile configuration id (-1: the digit-pairing
+                                kernel, which has one configuration per S)          */
+    int digit_products;      /* INT8: digit-plane products per K step (S^2, or
+                                S(S+1)/2 with digit pairing); FP64: 0               */
 } ff_plan_info;
 
 /* One fgemm of a batch or a server request: same meaning as the arguments

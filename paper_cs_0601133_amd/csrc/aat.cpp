@@ -73,6 +73,7 @@ int ff_faat(uint32_t p, int64_t m, int64_t k, uint32_t alpha, const uint32_t *A,
     }
     ff_opts po = o;
     po.winograd_levels = 0;
+    po.digit_pairing = 0; // the triangle's jobs use the regular digit kernel
     Plan P;
     if ((rc = make_plan(p, m, m, k, po, &P))) return rc;
     const int path = P.path;

@@ -252,22 +252,50 @@ void digit_weights(uint32_t p, uint32_t alpha, int bits, int S, uint32_t *w)
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-void i8_weights(I8Job &J, uint32_t alpha, int bits)
+// Digit pairing (S >= 2): with D_i = A_i B_i and, for t = 1 .. 2S-3,
+// K_t = sum over pairs i < j with i + j = t of (A_i + A_j)(B_i + B_j),
+//     sum_t R^t E_t = sum_t R^t K_t + sum_i D_i (R^(2i) - sum_{j != i} R^(i+j)),
+// because a_i b_j + a_j b_i = (a_i + a_j)(b_i + b_j) - a_i b_i - a_j b_j.
+// The pairing kernel's accumulator sets are D_0 .. D_{S-1}, then K_1 ..
+// K_{2S-3}; their weights (times alpha, mod p) follow.
+static void pairing_weights(uint32_t p, const uint32_t *w, int S, uint32_t *out)
+{
+    for (int i = 0; i < S; ++i) {
+        uint64_t x = w[2 * i];
+        for (int j = 0; j < S; ++j)
+            if (j != i) x += (uint64_t)(p - w[i + j]);
+        out[i] = (uint32_t)(x % p);
+    }
+    for (int t = 1; t <= 2 * S - 3; ++t) out[S + t - 1] = w[t];
+}
+
+void i8_weights(I8Job &J, uint32_t alpha, int bits, int pairing)
 {
     const int S = J.s;
     digit_weights(J.p, alpha, S == 1 ? 8 : bits, S, J.w);
+    int nset = 2 * S - 1;
+    if (pairing && S >= 2) {
+        uint32_t pw[12];
+        pairing_weights(J.p, J.w, S, pw);
+        nset = 3 * S - 3;
+        for (int t = 0; t < nset; ++t) J.w[t] = pw[t];
+    }
     const double h = (double)(J.p / 2);
-    for (int t = 0; t < 2 * S - 1; ++t)
+    for (int t = 0; t < nset; ++t)
         J.wc[t] = J.w[t] > J.p / 2 ? (double)J.w[t] - (double)J.p : (double)J.w[t];
     // every |E_t mod p| <= p/2 + 1 after the floating-point reduction
-    const double bound = (2.0 * S - 1.0) * h * (h + 1.0) + (double)J.p;
+    const double bound = (double)nset * h * (h + 1.0) + (double)J.p;
     J.fp_epi = bound <= 9007199254740992.0 ? 1 : 0;
     // |E_t| <= S * KP * (R/2)^2 (balanced digits, R = 2^bits; the direct
-    // plane's values are below 2^7); |wc_t| <= p/2.  When the whole sum
-    // stays below 2^53 it is exact in binary64 and one reduction suffices.
+    // plane's values are below 2^7); with pairing a set holds at most
+    // pairing_max_pairs(S) products of digit sums, each <= R^2; |wc_t| <= p/2.
+    // When the whole sum stays below 2^53 it is exact in binary64 and one
+    // reduction suffices.
     const double dmax = S == 1 ? 128.0 : (double)(1 << (bits - 1));
-    const double emax = (double)S * (double)J.KP * dmax * dmax;
-    J.epi_direct = J.fp_epi && (2.0 * S - 1.0) * h * emax + (double)J.p <= 9007199254740992.0;
+    const double emax = pairing && S >= 2
+                            ? (double)pairing_max_pairs(S) * (double)J.KP * 4.0 * dmax * dmax
+                            : (double)S * (double)J.KP * dmax * dmax;
+    J.epi_direct = J.fp_epi && (double)nset * h * emax + (double)J.p <= 9007199254740992.0;
 }
 
 // Packing task of one operand into centered doubles (row tile RT).
@@ -349,23 +377,30 @@ int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
                  int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const Plan &P,
                  void *ws, hipStream_t st)
 {
-    const I8Tile &t = i8_tile(P.tile);
+    // tile shape: the plan's configuration, or the pairing kernel's
+    const int bm = P.pairing ? i8p_bm(P.slices) : i8_tile(P.tile).bm();
+    const int bn = P.pairing ? i8p_bn(P.slices) : i8_tile(P.tile).bn();
+    const int gm = P.pairing ? 8 : i8_tile(P.tile).GM;
+    // planes per operand: the digits, and with pairing the digit sums
+    const int planes = P.pairing ? P.slices * (P.slices + 1) / 2 : P.slices;
     const int64_t kpass = std::min<int64_t>(k, P.kblock);
     const int KP = (int)round_up(kpass, I8_BK);
-    const int mp = (int)round_up(m, t.bm()), np = (int)round_up(n, t.bn());
+    const int mp = (int)round_up(m, bm), np = (int)round_up(n, bn);
     int8_t *Ad = (int8_t *)ws;
-    int8_t *Bd = Ad + (int64_t)P.slices * mp * KP;
+    int8_t *Bd = Ad + (int64_t)planes * mp * KP;
     for (int64_t k0 = 0; k0 < k; k0 += kpass) {
         const int kc = (int)std::min<int64_t>(kpass, k - k0);
         const int KPc = (int)round_up(kc, I8_BK);
         // A: rows m, element (i, l) of op(A)
         const uint32_t *Ak = transA ? A + k0 * lda : A + k0;
         SliceJob sa = slice_job(Ak, lda, (int)m, kc, transA, IN_RESIDUE, p, P.slices, P.bits,
-                                Ad, t.bm(), KPc);
+                                Ad, bm, KPc);
+        sa.pairs = P.pairing;
         // B^T: rows n, element (j, l) = op(B)(l, j)
         const uint32_t *Bk = transB ? B + k0 : B + k0 * ldb;
         SliceJob sb = slice_job(Bk, ldb, (int)n, kc, transB ? 0 : 1, IN_RESIDUE, p, P.slices,
-                                P.bits, Bd, t.bn(), KPc);
+                                P.bits, Bd, bn, KPc);
+        sb.pairs = P.pairing;
         FF_HIP_CHECK(FF_TIMED(PROF_SLICE, st, launch_slice2(sa, sb, st)));
         I8Job J;
         std::memset(&J, 0, sizeof(J));
@@ -373,10 +408,13 @@ int run_i8_plain(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64
         J.C = C; J.ldc = ldc; J.m = (int)m; J.n = (int)n; J.KP = KPc; J.s = P.slices;
         J.p = p; J.beta = k0 == 0 ? beta : 1u;
         J.pd = (double)p; J.pinv = 1.0 / (double)p;
-        i8_weights(J, alpha, P.bits);
-        J.gm = t.GM;
-        J.tiles_m = mp / t.bm(); J.tiles_n = np / t.bn();
-        FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_i8(P.tile, J, st)));
+        i8_weights(J, alpha, P.bits, P.pairing);
+        J.gm = gm;
+        J.tiles_m = mp / bm; J.tiles_n = np / bn;
+        if (P.pairing)
+            FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_i8_pair(J, st)));
+        else
+            FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_i8(P.tile, J, st)));
     }
     return FF_OK;
 }
@@ -422,7 +460,7 @@ namespace ff {
 static int plan_call(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o, Plan *P)
 {
     if (o.path == FF_PATH_AUTO && o.digit_bits == 0 && o.winograd_levels <= 0 &&
-        f64_small(m, n, k)) {
+        !o.digit_pairing && f64_small(m, n, k)) {
         ff_opts fo = o;
         fo.path = FF_PATH_FP64;
         if (make_plan(p, m, n, k, fo, P) == FF_OK && P->small) return FF_OK;
@@ -474,6 +512,8 @@ int ff_plan_query(uint32_t p, int transA, int transB, int64_t m, int64_t n, int6
     out->kblock = P.kblock;
     out->workspace_bytes = P.ws_bytes;
     out->tile_config = P.tile;
+    out->digit_products = P.path != FF_PATH_INT8 ? 0
+                          : P.pairing ? P.slices * (P.slices + 1) / 2 : P.slices * P.slices;
     return FF_OK;
 }
 

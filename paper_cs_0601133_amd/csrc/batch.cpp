@@ -243,6 +243,7 @@ int job_from_abi(const ff_job &a, const ff_opts &o, IJob *out)
     }
     ff_opts po = o;
     po.winograd_levels = 0;
+    po.digit_pairing = 0; // batches use the regular digit kernel
     Plan P;
     if ((rc = make_plan(a.p, a.m, a.n, a.k, po, &P))) return rc;
     j.path = P.path;
@@ -282,7 +283,7 @@ int prep_abi_batch(const ff_job *jobs, int njobs, const ff_opts &o, BatchPrep *B
     int tile;
     if (path == FF_PATH_INT8) {
         tile = tuned_i8_tile(Smax, big_m, big_n, big_k);
-        if (tile < 0) tile = i8_batch_tile(Smax);
+        if (tile < 0) tile = i8_default_tile(Smax);
     } else {
         tile = choose_f64_tile();
     }

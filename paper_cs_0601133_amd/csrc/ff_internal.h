@@ -72,8 +72,6 @@ struct I8Tile {
 int i8_tile_count();
 const I8Tile &i8_tile(int id);
 int i8_default_tile(int S);
-// Default for persistent batched launches.
-int i8_batch_tile(int S);
 // Tile chosen by the autotuner for this slice count and size, or -1.
 int tuned_i8_tile(int S, int64_t m, int64_t n, int64_t k);
 constexpr int I8_BK = 64;
@@ -91,6 +89,7 @@ struct Plan {
     int64_t max_prod = 0;    // bound on |a*b| of one leaf product term
     int64_t kblock = 0;      // FP64: products between folds; INT8: K per pass
     int tile = 0;
+    int pairing = 0;         // INT8: products of digit sums for the cross terms
     int small = 0;           // FP64 without Winograd in one launch (no workspace)
     int64_t ws_bytes = 0;
     // leaf problem shape (after peeling the top level to multiples of 2^L)
@@ -169,6 +168,8 @@ struct SliceJob {
     int in_mode;        // IN_RESIDUE (center with p) or IN_SIGNED
     uint32_t p;
     int S, bits;        // S == 0: one plane of doubles for the FP64 kernel
+    int pairs;          // after the S digit planes, the S(S-1)/2 planes of
+                        // digit sums d_i + d_j (i < j, lexicographic order)
     int8_t *D;          // packed planes
     int RT;             // row tile of the packing
     int rows_pad, KP;   // padded sizes
@@ -187,8 +188,10 @@ struct I8Job {
     int s;              // digits of this job (<= kernel's S)
     uint32_t p, beta;
     double pd, pinv;
-    uint32_t w[9];      // alpha * R^t mod p, t = 0 .. 2s-2
-    double wc[9];       // the same weights centered, as doubles
+    uint32_t w[12];     // weight of each accumulator set: alpha * R^t mod p for
+                        // E_t, t = 0 .. 2s-2 (digit pairing: the 3s-3 sets of
+                        // the pairing kernel, see i8_weights)
+    double wc[12];      // the same weights centered, as doubles
     int fp_epi;         // recombine in binary64: (2s-1)(p/2)(p/2+1) + p <= 2^53
     int epi_direct;     // sum wc_t E_t exactly in binary64 without reducing each E_t:
                         // (2s-1) max|wc_t| max|E_t| + p <= 2^53 for this job's K
@@ -197,8 +200,28 @@ struct I8Job {
     int tile_start;
 };
 
-// Fills w, wc and fp_epi of an INT8 job for digit width bits.
-void i8_weights(I8Job &J, uint32_t alpha, int bits);
+// Fills w, wc and fp_epi of an INT8 job for digit width bits; with
+// pairing, the weights of the pairing kernel's accumulator sets.
+void i8_weights(I8Job &J, uint32_t alpha, int bits, int pairing = 0);
+
+// Digit pairing (kernels_i8p.hip): workgroup tile i8p_bm(S) x i8p_bn(S)
+// for S in 2..5; the digit planes and digit-sum planes are packed with row
+// tiles of these heights.
+inline int i8p_bm(int S) { return S >= 5 ? 64 : 128; }
+inline int i8p_bn(int) { return 64; }
+// Largest number of pairs i < j < S with the same i + j.
+inline int pairing_max_pairs(int S)
+{
+    int best = 0;
+    for (int t = 1; t <= 2 * S - 3; ++t) {
+        int c = 0;
+        for (int i = 0; i < S; ++i)
+            for (int j = i + 1; j < S; ++j) c += i + j == t;
+        best = c > best ? c : best;
+    }
+    return best;
+}
+hipError_t launch_i8_pair(const I8Job &J, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files)

@@ -107,10 +107,20 @@ __device__ __forceinline__ bool load_unit(const SliceJob &J, int b, UnitTile &ti
     return unit_from_raw(J, b, tile, w, v, r, kc);
 }
 
+// Sum of two words of four signed bytes, byte by byte modulo 256 (no carry
+// from one byte into the next): the low seven bits of each byte are added,
+// and the top bit is the sum of the top bits and that carry, modulo 2.
+__device__ __forceinline__ uint32_t add_bytes(uint32_t x, uint32_t y)
+{
+    const uint32_t low = (x & 0x7F7F7F7Fu) + (y & 0x7F7F7F7Fu);
+    return low ^ ((x ^ y) & 0x80808080u);
+}
+
 // Writes the S balanced digits of the 16 values of unit (r, kc) into the
 // packed planes at D (layout of the digit slicer: the 16-byte group (r, kc)
-// of digit d at d*plane + (r/RT)*RT*KP + kc*RT*16 + (r%RT)*16).  v is
-// consumed.
+// of digit d at d*plane + (r/RT)*RT*KP + kc*RT*16 + (r%RT)*16); with
+// J.pairs, planes S .. S(S+1)/2 - 1 then take the digit sums d_i + d_j,
+// i < j (7-bit digits: the sums fit a signed byte).  v is consumed.
 __device__ __forceinline__ void write_digits(const SliceJob &J, int8_t *D, int32_t *v, int r,
                                              int kc)
 {
@@ -118,18 +128,48 @@ __device__ __forceinline__ void write_digits(const SliceJob &J, int8_t *D, int32
     const int sh = 32 - bits;
     int8_t *dst = D + (int64_t)(r / J.RT) * J.RT * J.KP + (int64_t)kc * J.RT * 16 +
                   (int64_t)(r % J.RT) * 16;
-    for (int d = 0; d < J.S; ++d) {
-        uint32_t w[4] = {0, 0, 0, 0};
+    if (!J.pairs) {
+        for (int d = 0; d < J.S; ++d) {
+            uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            // balanced digit: the value in [-R/2, R/2) congruent to v mod R,
-            // i.e. the low `bits` bits sign-extended
-            const int dig = (int)((uint32_t)v[e] << sh) >> sh;
-            v[e] = (v[e] - dig) >> bits; // exact division by R
-            w[e >> 2] |= (uint32_t)(dig & 0xFF) << (8 * (e & 3));
+            for (int e = 0; e < 16; ++e) {
+                // balanced digit: the value in [-R/2, R/2) congruent to v mod
+                // R, i.e. the low `bits` bits sign-extended
+                const int dig = (int)((uint32_t)v[e] << sh) >> sh;
+                v[e] = (v[e] - dig) >> bits; // exact division by R
+                w[e >> 2] |= (uint32_t)(dig & 0xFF) << (8 * (e & 3));
+            }
+            *(uint4 *)(dst + (int64_t)d * J.plane) = make_uint4(w[0], w[1], w[2], w[3]);
         }
-        *(uint4 *)(dst + (int64_t)d * J.plane) = make_uint4(w[0], w[1], w[2], w[3]);
+        return;
     }
+    // digit pairing (S <= 5): the digits stay in registers for the sums
+    uint4 dw[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        uint32_t w[4] = {0, 0, 0, 0};
+        if (d < J.S) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int dig = (int)((uint32_t)v[e] << sh) >> sh;
+                v[e] = (v[e] - dig) >> bits;
+                w[e >> 2] |= (uint32_t)(dig & 0xFF) << (8 * (e & 3));
+            }
+            *(uint4 *)(dst + (int64_t)d * J.plane) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        dw[d] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    int pl = J.S;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 5; ++j)
+            if (j < J.S) {
+                *(uint4 *)(dst + (int64_t)pl * J.plane) =
+                    make_uint4(add_bytes(dw[i].x, dw[j].x), add_bytes(dw[i].y, dw[j].y),
+                               add_bytes(dw[i].z, dw[j].z), add_bytes(dw[i].w, dw[j].w));
+                ++pl;
+            }
 }
 
 // Writes the 16 values of unit (r, kc) as binary64 into the packed operand

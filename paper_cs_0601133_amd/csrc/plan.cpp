@@ -233,12 +233,24 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         return fail(FF_EINVAL, "winograd_levels must be -1..3");
     if (o.preadd_mode < 0 || o.preadd_mode > 2)
         return fail(FF_EINVAL, "preadd_mode must be 0, 1 or 2");
+    if (o.digit_pairing != 0 && o.digit_pairing != 1)
+        return fail(FF_EINVAL, "digit_pairing must be 0 or 1");
+    if (o.digit_pairing) {
+        // sums of two digits must fit int8: 7-bit digits, on the INT8 path,
+        // without Winograd levels
+        if (o.path == FF_PATH_FP64)
+            return fail(FF_EUNSUPPORTED, "digit pairing is an INT8-path option");
+        if (o.digit_bits == 8)
+            return fail(FF_EUNSUPPORTED, "digit pairing needs 7-bit digits");
+        if (o.winograd_levels > 0)
+            return fail(FF_EUNSUPPORTED, "digit pairing runs plain products only");
+    }
 
     const Range base{-(int64_t)(p / 2), (int64_t)((p - 1) / 2)};
 
     // Winograd levels: requested or from the crossover orders, for the
     // path this call takes and its digit count without Winograd.
-    int L = o.winograd_levels;
+    int L = o.digit_pairing ? 0 : o.winograd_levels;
     const int64_t dmin = std::min({m, n, k});
     int path = o.path == FF_PATH_AUTO ? FF_PATH_INT8 : o.path;
     if (L < 0) {
@@ -300,6 +312,7 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
             Range r = reduce ? wid_r : wid_d;
             for (int bits : {7, 8}) {
                 if (o.digit_bits && bits != o.digit_bits) continue;
+                if (o.digit_pairing && bits != 7) continue;
                 int s = slices_for(r, bits);
                 if (s == 0) continue;
                 // fewer slices wins; ties keep the delayed (unreduced) form and
@@ -321,13 +334,28 @@ int make_plan(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
         const int64_t d = digit_mag(r, best_bits, best_s);
         P.kblock = I32MAX / ((int64_t)best_s * d * d);
         P.tile = choose_i8_tile(best_s, P.me >> L, P.ne >> L, P.ke >> L, o);
+        if (o.digit_pairing && best_s >= 2) {
+            // accumulators: products of one digit pair (|.| <= d^2 each) and
+            // sums over the pairs of one weight of products of digit sums
+            // (|.| <= (2d)^2 each)
+            P.pairing = 1;
+            P.tile = -1;
+            const int64_t q = (int64_t)pairing_max_pairs(best_s) * 4 * d * d;
+            P.kblock = std::min(I32MAX / (d * d), I32MAX / q);
+        }
     }
 
     // Workspace.
     const int64_t ml = P.me >> L, nl = P.ne >> L, kl = P.ke >> L;
     const int64_t nleaf = ipow7(L);
     int64_t ws = 0;
-    if (P.path == FF_PATH_INT8) {
+    if (P.path == FF_PATH_INT8 && P.pairing) {
+        const int64_t kpass = std::min<int64_t>(kl, P.kblock);
+        const int64_t KP = round_up(std::max<int64_t>(kpass, 1), I8_BK);
+        const int64_t mp = round_up(std::max<int64_t>(ml, 1), i8p_bm(P.slices));
+        const int64_t np = round_up(std::max<int64_t>(nl, 1), i8p_bn(P.slices));
+        ws += (int64_t)P.slices * (P.slices + 1) / 2 * (mp + np) * KP;
+    } else if (P.path == FF_PATH_INT8) {
         const I8Tile &t = i8_tile(P.tile);
         const int64_t kpass = std::min<int64_t>(kl, P.kblock);
         const int64_t KP = round_up(std::max<int64_t>(kpass, 1), I8_BK);

@@ -43,14 +43,15 @@ _VP = ctypes.c_void_p
 
 class ff_opts(ctypes.Structure):
     _fields_ = [("path", _INT), ("winograd_levels", _INT), ("digit_bits", _INT),
-                ("validate", _INT), ("preadd_mode", _INT), ("stream", _VP)]
+                ("validate", _INT), ("preadd_mode", _INT), ("stream", _VP),
+                ("digit_pairing", _INT)]
 
 
 class ff_plan_info(ctypes.Structure):
     _fields_ = [("path", _INT), ("winograd_levels", _INT), ("preadds_reduced", _INT),
                 ("digit_bits", _INT), ("slices", _INT), ("operand_lo", _I64),
                 ("operand_hi", _I64), ("max_abs_product", _I64), ("kblock", _I64),
-                ("workspace_bytes", _I64), ("tile_config", _INT)]
+                ("workspace_bytes", _I64), ("tile_config", _INT), ("digit_products", _INT)]
 
 
 class ff_job(ctypes.Structure):
@@ -186,8 +187,9 @@ def _ld(x, default):
 
 
 def make_opts(path=FF_PATH_AUTO, winograd_levels=-1, digit_bits=0, validate=0,
-              preadd_mode=0, stream=None):
-    return ff_opts(path, winograd_levels, digit_bits, validate, preadd_mode, stream)
+              preadd_mode=0, stream=None, digit_pairing=0):
+    return ff_opts(path, winograd_levels, digit_bits, validate, preadd_mode, stream,
+                   digit_pairing)
 
 
 def _torch_stream():

@@ -259,3 +259,34 @@ def test_bad_options():
         with pytest.raises(ff.FFError) as e:
             ff.ff_plan_query(7, 0, 0, 8, 8, 8, o)
         assert e.value.status == ff.FF_EINVAL
+
+
+def test_plan_digit_pairing():
+    # 7-bit digits with products of digit sums for the cross terms: S(S+1)/2
+    # digit products, S(S+1)/2 planes per operand, and an int32 K-block from
+    # the largest set of sum products sharing one weight (two pairs for
+    # S = 4 and 5: 2 * 128^2 per step)
+    o = ff.make_opts(path=ff.FF_PATH_INT8, digit_pairing=1)
+    for p, S, kb in ((8191, 2, 131071), (65521, 3, 131071), (8388593, 4, 65535),
+                     (2147483647, 5, 65535)):
+        i = ff.ff_plan_query(p, 0, 0, 4096, 4096, 4096, o)
+        assert (i.slices, i.digit_bits, i.digit_products) == (S, 7, S * (S + 1) // 2), p
+        assert i.kblock == kb and i.winograd_levels == 0 and i.tile_config == -1, p
+        bm = 64 if S == 5 else 128
+        assert i.workspace_bytes == S * (S + 1) // 2 * (4096 // bm * bm + 4096) * 4096, p
+        plain = ff.ff_plan_query(p, 0, 0, 4096, 4096, 4096,
+                                 ff.make_opts(path=ff.FF_PATH_INT8, digit_bits=7,
+                                              winograd_levels=0))
+        assert plain.digit_products == S * S and plain.slices == S
+    # one direct plane: nothing to pair
+    i = ff.ff_plan_query(251, 0, 0, 256, 256, 256, o)
+    assert i.slices == 1 and i.digit_products == 1
+    for bad, status in ((dict(path=ff.FF_PATH_FP64, digit_pairing=1), ff.FF_EUNSUPPORTED),
+                        (dict(path=ff.FF_PATH_INT8, digit_bits=8, digit_pairing=1),
+                         ff.FF_EUNSUPPORTED),
+                        (dict(path=ff.FF_PATH_INT8, winograd_levels=1, digit_pairing=1),
+                         ff.FF_EUNSUPPORTED),
+                        (dict(digit_pairing=2), ff.FF_EINVAL)):
+        with pytest.raises(ff.FFError) as e:
+            ff.ff_plan_query(8388593, 0, 0, 512, 512, 512, ff.make_opts(**bad))
+        assert e.value.status == status, bad

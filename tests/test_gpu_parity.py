@@ -220,8 +220,9 @@ def _full_4096():
     return _FULL_4096["args"], _FULL_4096["want"]
 
 
-@pytest.mark.parametrize("opts", PATHS + [dict(path=INT8, digit_bits=7, winograd_levels=1)],
-                         ids=["fp64", "int8d7", "int8d8", "int8d7_winograd1"])
+@pytest.mark.parametrize("opts", PATHS + [dict(path=INT8, digit_bits=7, winograd_levels=1),
+                                          dict(path=INT8, digit_pairing=1)],
+                         ids=["fp64", "int8d7", "int8d8", "int8d7_winograd1", "int8d7_pairing"])
 def test_full_size_4096(opts):
     # m = n = k = 4096, p = 8388593, alpha = 3, beta = 5 (the benchmark's
     # workload and launch configuration): every entry against the oracle
