@@ -292,12 +292,15 @@ hipError_t launch_trsm_leaf(const uint32_t *Tn, int64_t ldn, const uint32_t *Tin
 
 // LQUP (kernels_lqup.hip): rows and window columns of one pivot panel.
 constexpr int LQUP_PANEL = 64;
-constexpr int LQUP_WINDOW = 128;
+constexpr int LQUP_WINDOW = 64;
 // Factors rows [i0, i0 + nr) over columns [k, k + W) (every entry already
 // reduced by the pivots above); out as described in kernels_lqup.hip
 // (3 + 2 LQUP_PANEL int32).  whole: the window reaches the last column.
+// fail (may be null): set to 1 when the panel does not find nr pivots in
+// their own columns (a dependent row, a stop, or a column exchange).
 hipError_t launch_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
-                             int whole, uint32_t p, int32_t *out, hipStream_t st);
+                             int whole, uint32_t p, int32_t *out, hipStream_t st,
+                             int32_t *fail = nullptr);
 // Column exchanges pairs[2j] <-> pairs[2j + 1] in order, rows outside
 // [skip_lo, skip_hi).
 hipError_t launch_lqup_swap(uint32_t *A, int64_t lda, int64_t m, int64_t skip_lo, int64_t skip_hi,

@@ -19,7 +19,7 @@ constexpr int PW = LQUP_WINDOW;   // columns of the panel's window
 constexpr int PT = 1024;          // threads: PW columns x PG row groups
 constexpr int PG = PT / PW;       // row groups
 constexpr int PQ = PR / PG;       // rows per group
-static_assert(PR == 64 && PW == 128, "panel: column tid % 128, rows 8 (tid / 128) + q");
+static_assert(PR == 64 && PW == 64, "panel: column tid % 64, rows 4 (tid / 64) + q");
 
 __device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 {
@@ -39,16 +39,18 @@ __device__ __forceinline__ uint32_t inv_mod(uint32_t a, uint32_t p)
 }
 
 // One panel: rows [i0, i0 + nr) (nr <= 64) over the window of columns
-// [k, k + W) (W <= 128), every entry already reduced by the pivots above.
+// [k, k + W) (W <= 64), every entry already reduced by the pivots above.
 // Thread (c, g) owns column c of the window and the contiguous rows
-// 8g .. 8g + 7; the walk over rows unrolls and a group whose rows are all
+// 4g .. 4g + 3; the walk over rows unrolls and a group whose rows are all
 // above the pivot row skips the update (the test is uniform per wave).
 // Rows are processed in order: a row pivots on its first nonzero entry at or
 // after column t (the next pivot index), exchanged into column t inside the
 // panel; a row with no such entry is dependent if the window reaches the
 // last column (whole), else the panel stops there (the caller searches the
-// columns past the window).  A window of 128 columns for 64 rows leaves
-// every row at least 64 candidate columns.
+// columns past the window).  A window of 64 columns holds the pivots of
+// all 64 rows when they are independent there (the usual case); a
+// 128-column window (twice the update work per row) measured 13% slower
+// over a whole factorisation at 4096.
 //
 // Elimination is fraction free: below pivot row r (pivot value pi, entry a
 // of row r2 in column t) row r2 <- pi row r2 - a row r on the columns after
@@ -64,10 +66,13 @@ __device__ __forceinline__ uint32_t inv_mod(uint32_t a, uint32_t p)
 // out: [0] pivots t, [1] rows processed, [2] stuck, [3 + r] = pivot index
 // of processed row r or -1 (dependent), [3 + 64 + j] = window column that
 // pivot j came from (== j: no exchange).
+//
+// fail (may be null): set to 1 unless every row of the panel pivots in its
+// own column (the full-rank guess of the caller's fast path).
 template <bool EXACT>
 __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr,
                                                    int64_t k, int W, int whole, uint32_t p,
-                                                   double pinv, int32_t *out)
+                                                   double pinv, int32_t *out, int32_t *fail)
 {
     // published pivot row, column t and search results, double-buffered by
     // row parity so that a row's writes never meet the previous row's reads
@@ -100,7 +105,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
     }
     __syncthreads();
 
-    int t = 0, nproc = 0, stuck = 0;
+    int t = 0, nproc = 0, stuck = 0, exchanged = 0;
     // every loop has a constant trip count (it unrolls; v[] stays in
     // registers); rows past nr and rows after a stop are skipped by tests
     // that are uniform across the workgroup
@@ -135,6 +140,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
             continue;
         }
         if (cmin != t) {
+            exchanged = 1;
             // exchange columns t and cmin in every row of the panel, then
             // publish the new column t and row r's two changed entries
             if (c == t) {
@@ -231,6 +237,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
         out[0] = t;
         out[1] = nproc;
         out[2] = stuck;
+        if (fail && (t != nr || stuck || exchanged)) *fail = 1;
     }
     if (tid < PR) out[3 + tid] = s_rowpiv[tid];
 }
@@ -309,17 +316,17 @@ __global__ __launch_bounds__(256) void k_lqup_first_nonzero(const uint32_t *A, i
 } // namespace
 
 hipError_t launch_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
-                             int whole, uint32_t p, int32_t *out, hipStream_t st)
+                             int whole, uint32_t p, int32_t *out, hipStream_t st, int32_t *fail)
 {
     if (nr < 1 || nr > PR || W < 1 || W > PW) return hipErrorInvalidValue;
     const double h = (double)(p / 2) + 2.0;
     const bool exact = 2.0 * h * h <= 9007199254740992.0;
     if (exact)
         hipLaunchKernelGGL(k_lqup_panel<true>, dim3(1), dim3(PT), 0, st, A, lda, i0, nr, k, W,
-                           whole, p, 1.0 / (double)p, out);
+                           whole, p, 1.0 / (double)p, out, fail);
     else
         hipLaunchKernelGGL(k_lqup_panel<false>, dim3(1), dim3(PT), 0, st, A, lda, i0, nr, k, W,
-                           whole, p, 1.0 / (double)p, out);
+                           whole, p, 1.0 / (double)p, out, fail);
     return hipGetLastError();
 }
 

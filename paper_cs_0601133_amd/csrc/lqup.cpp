@@ -13,7 +13,7 @@
 // the bottom half [X Z] solve G T = X (the right-hand triangular solve, done
 // as T^T G^T = X^T with ftrsm on transposes), update Z <- Z - G Y with one
 // fgemm, and factor Z.  Blocks of 64 rows are factored by one workgroup
-// over a window of 128 columns (k_lqup_panel); the pivot rows' entries past
+// over a window of 64 columns (k_lqup_panel); the pivot rows' entries past
 // the window are then finished with a unit lower triangular ftrsm and the
 // panel's remaining rows with an fgemm.  When a row's window holds no pivot,
 // the remaining rows of the panel are searched over all columns from the
@@ -22,6 +22,16 @@
 // rows before it are dependent.  Each panel's pivots
 // decide the sizes of what follows, so the host reads them back: the call is
 // synchronous.
+//
+// Fast path: when m <= n the factorisation first runs on the guess that
+// every row is a pivot row in its own column (no dependent row, no column
+// exchange), which fixes every size in advance: nothing is read back per
+// panel, the pivot rows of a half are its rows in place (no gather), and
+// each panel kernel records in a device flag whether the guess held for it.
+// The flag is read once at the end; if any panel saw otherwise, A is
+// restored from a copy taken at the start and the factorisation runs again
+// with the read-backs above.  Either way the result is the same unique
+// factorisation.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -42,6 +52,8 @@ struct Lqup {
     std::vector<int64_t> piv; // pivot rows in order
     std::vector<char> dep;    // dependent rows
     std::vector<int64_t> colperm;
+    bool spec = false;      // full-rank guess in force (see above)
+    int32_t *d_fail = nullptr; // set by a panel that contradicts the guess
     // device scratch (workspace slot 2)
     uint32_t *U = nullptr;  // gathered pivot rows
     uint32_t *Xt = nullptr; // transposed X
@@ -70,9 +82,32 @@ int exchange(Lqup &c, const std::vector<int64_t> &pairs, int64_t skip_lo, int64_
     return FF_OK;
 }
 
+// Fast-path panel: rows [a, b) assumed to be pivot rows in columns
+// [c.k, c.k + b - a) in order; the kernel flags the guess if it fails.
+int panel_guess(Lqup &c, int64_t a, int64_t b, int64_t *found)
+{
+    const int nr = (int)(b - a);
+    const int W = (int)std::min<int64_t>(LQUP_WINDOW, c.n - c.k);
+    const int whole = c.k + W == c.n;
+    FF_HIP_CHECK(launch_lqup_panel(c.A, c.lda, a, nr, c.k, W, whole, c.p, c.d_out, c.st,
+                                   c.d_fail));
+    if (!whole && nr <= W) {
+        const int64_t nc = c.n - c.k - W;
+        uint32_t *T = c.A + a * c.lda + c.k;
+        int rc = ff_ftrsm_ex(c.p, FF_LOWER, FF_NOTRANS, FF_UNIT, nr, nc, 1, T, c.lda,
+                             c.A + a * c.lda + c.k + W, c.lda, &c.o);
+        if (rc) return rc;
+    }
+    for (int64_t r = a; r < b; ++r) c.piv.push_back(r);
+    c.k += nr;
+    *found = nr;
+    return FF_OK;
+}
+
 // Rows [a, b), b - a <= LQUP_PANEL; the pivots found go to *found.
 int panel(Lqup &c, int64_t a, int64_t b, int64_t *found)
 {
+    if (c.spec) return panel_guess(c, a, b, found);
     const int64_t k_start = c.k;
     int64_t i = a;
     int32_t out[3 + 2 * LQUP_PANEL];
@@ -153,18 +188,26 @@ int rec(Lqup &c, int64_t a, int64_t b, int64_t *found)
     if (rc) return rc;
     const int64_t m2 = b - mid, nc = c.n - k0;
     if (r1 > 0 && m2 > 0) {
-        // T (r1 x r1 upper) and Y: the U rows of the top half's pivots
-        rc = upload_async(c.st, c.piv.data() + k0, r1 * sizeof(int64_t), c.d_rows);
-        if (rc) return rc;
-        FF_HIP_CHECK(launch_lqup_gather(c.A, c.lda, c.d_rows, r1, k0, nc, c.U, nc, c.st));
+        // T (r1 x r1 upper) and Y: the U rows of the top half's pivots (on
+        // the fast path, the top half's rows themselves)
+        const uint32_t *U = c.U;
+        int64_t ldu = nc;
+        if (c.spec) {
+            U = c.A + a * c.lda + k0;
+            ldu = c.lda;
+        } else {
+            rc = upload_async(c.st, c.piv.data() + k0, r1 * sizeof(int64_t), c.d_rows);
+            if (rc) return rc;
+            FF_HIP_CHECK(launch_lqup_gather(c.A, c.lda, c.d_rows, r1, k0, nc, c.U, nc, c.st));
+        }
         // G T = X  <=>  T^T G^T = X^T
         uint32_t *X = c.A + mid * c.lda + k0;
         FF_HIP_CHECK(launch_lqup_transpose(X, c.lda, m2, r1, c.Xt, m2, c.st));
-        rc = ff_ftrsm_ex(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r1, m2, 1, c.U, nc, c.Xt, m2, &c.o);
+        rc = ff_ftrsm_ex(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r1, m2, 1, U, ldu, c.Xt, m2, &c.o);
         if (rc) return rc;
         FF_HIP_CHECK(launch_lqup_transpose(c.Xt, m2, r1, m2, X, c.lda, c.st));
         if (nc > r1) {
-            rc = fgemm_sub(c, m2, nc - r1, r1, X, c.lda, c.U + r1, nc, X + r1, c.lda);
+            rc = fgemm_sub(c, m2, nc - r1, r1, X, c.lda, U + r1, ldu, X + r1, c.lda);
             if (rc) return rc;
         }
     }
@@ -242,9 +285,38 @@ int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
     c.d_pairs = (int64_t *)(w + u_bytes + x_bytes + rows_bytes);
     c.d_out = (int32_t *)(w + u_bytes + x_bytes + rows_bytes + pairs_bytes);
     c.d_first = (int64_t *)(w + u_bytes + x_bytes + rows_bytes + pairs_bytes + out_bytes);
+    c.d_fail = (int32_t *)(c.d_out + 3 + 2 * LQUP_PANEL);
     int64_t found = 0;
-    rc = rec(c, 0, m, &found);
-    if (rc) return rc;
+    bool guessed = false;
+    if (m <= n) {
+        // fast path: keep a copy of A, clear the flag, run on the guess
+        void *bk = nullptr;
+        if ((rc = workspace(c.st, (size_t)(m * n * 4), &bk, 3))) return rc;
+        FF_HIP_CHECK(hipMemcpy2DAsync(bk, (size_t)n * 4, A, (size_t)lda * 4, (size_t)n * 4,
+                                      (size_t)m, hipMemcpyDeviceToDevice, c.st));
+        FF_HIP_CHECK(launch_scale((uint32_t *)c.d_fail, 1, 1, 1, 2u, 0u, c.st));
+        c.spec = true;
+        rc = rec(c, 0, m, &found);
+        if (rc) return rc;
+        int32_t failed = 1;
+        FF_HIP_CHECK(hipMemcpyAsync(&failed, c.d_fail, sizeof(failed), hipMemcpyDeviceToHost,
+                                    c.st));
+        FF_HIP_CHECK(hipStreamSynchronize(c.st));
+        guessed = failed == 0;
+        if (!guessed) {
+            FF_HIP_CHECK(hipMemcpy2DAsync(A, (size_t)lda * 4, bk, (size_t)n * 4, (size_t)n * 4,
+                                          (size_t)m, hipMemcpyDeviceToDevice, c.st));
+            c.spec = false;
+            c.k = 0;
+            c.piv.clear();
+            c.dep.assign(m, 0);
+            for (int64_t j = 0; j < n; ++j) c.colperm[j] = j;
+        }
+    }
+    if (!guessed) {
+        rc = rec(c, 0, m, &found);
+        if (rc) return rc;
+    }
     FF_HIP_CHECK(hipStreamSynchronize(c.st));
     *rank = c.k;
     int64_t d = 0;
