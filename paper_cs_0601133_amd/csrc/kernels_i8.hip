@@ -492,17 +492,13 @@ const I8Tile k_tiles[] = {
     FF_I8_TILES(FF_ROW)
 #undef FF_ROW
 };
-// Default configuration per slice count (index = S), for single products
-// and for persistent batches (whose tile loop must also hold the job
-// table's fields: configurations that stay within 256 VGPRs there).
+// Default configuration per slice count (index = S).
 const int k_default[6] = {-1, 20, 4, 6, 15, 12};
-const int k_batch_default[6] = {-1, 20, 18, 16, 15, 12};
 } // namespace
 
 int i8_tile_count() { return (int)(sizeof(k_tiles) / sizeof(k_tiles[0])); }
 const I8Tile &i8_tile(int id) { return k_tiles[id]; }
 int i8_default_tile(int S) { return (S >= 1 && S <= 5) ? k_default[S] : -1; }
-int i8_batch_tile(int S) { return (S >= 1 && S <= 5) ? k_batch_default[S] : -1; }
 
 hipError_t launch_i8(int tile, const I8Job &J, hipStream_t st)
 {

@@ -284,7 +284,7 @@ bool Server::admit_locked()
             for (const IJob &j : jobs)
                 if (j.m * j.n * j.k > bm * bn * bk) { bm = j.m; bn = j.n; bk = j.k; }
             tile = tuned_i8_tile(Smax, bm, bn, bk);
-            if (tile < 0) tile = i8_batch_tile(Smax);
+            if (tile < 0) tile = i8_default_tile(Smax);
         } else {
             tile = choose_f64_tile();
         }
