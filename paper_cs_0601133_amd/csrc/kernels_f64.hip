@@ -238,9 +238,24 @@ __device__ __forceinline__ void f64_tile(const F64Job &J, int tm, int tn, char *
 
     // Epilogue: in each 16 x 16 block the lane holds column lane%16 of rows
     // lane/16 + 4r, r = 0..3 (v_mfma_f64_16x16x4 result layout).
+    // C is read a block row (16 entries) at a time before that row's
+    // stores, clamped into C so that no branch surrounds the loads: one
+    // memory round trip per block row, not one per entry behind each store
+    // (a load after a store to C cannot be moved above it).
     const int m0 = tm * C::BM, n0 = tn * C::BN;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+        uint32_t cin[4][4];
+        if (J.beta && !J.part) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gr = m0 + wm0 + i * 16 + (lane >> 4) + 4 * r;
+                    const int gc = n0 + wn0 + j * 16 + (lane & 15);
+                    cin[j][r] = J.C[(int64_t)min(gr, J.m - 1) * J.ldc + min(gc, J.n - 1)];
+                }
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -254,11 +269,11 @@ __device__ __forceinline__ void f64_tile(const F64Job &J, int tm, int tn, char *
                         continue;
                     }
                     uint32_t out = mulmod(J.alpha, v, J.p, J.pinv);
-                    uint32_t *cp = J.C + (int64_t)gr * J.ldc + gc;
-                    if (J.beta) out = addmod(out, mulmod(J.beta, *cp, J.p, J.pinv), J.p);
-                    *cp = out;
+                    if (J.beta) out = addmod(out, mulmod(J.beta, cin[j][r], J.p, J.pinv), J.p);
+                    J.C[(int64_t)gr * J.ldc + gc] = out;
                 }
             }
+    }
 }
 
 // FINE (reduction after every matrix-core step) is a separate instantiation

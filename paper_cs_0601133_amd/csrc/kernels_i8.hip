@@ -270,11 +270,29 @@ __device__ __forceinline__ void i8_tile(const I8Job &J, int tm, int tn, char *sm
     // digit sums are recombined in one exact binary64 sum with centered
     // weights; with fp_epi each E_t is first reduced (centered) in binary64;
     // otherwise 64-bit integers with a reduction per term.
+    //
+    // The entries of C of each 32 x 32 block are requested together before
+    // its recombination: a load placed after a store to C cannot be moved
+    // above it (the addresses may alias for all the compiler knows), so
+    // reading each entry next to its store would wait out one memory round
+    // trip per entry; requested together, their latency overlaps the
+    // recombination (one round trip per block, 16 registers).
     const int m0 = tm * C::BM, n0 = tn * C::BN;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TN; ++j) {
+            uint32_t cin[16];
+            if (J.beta) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int row = m0 + wm0 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    const int col = n0 + wn0 + 32 * j + (lane & 31);
+                    // clamped into C: no branch around the load (an entry
+                    // outside C is read from the edge and never used)
+                    cin[v] = J.C[(int64_t)min(row, J.m - 1) * J.ldc + min(col, J.n - 1)];
+                }
+            }
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int row = m0 + wm0 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -303,11 +321,11 @@ __device__ __forceinline__ void i8_tile(const I8Job &J, int tm, int tn, char *sm
                             r = addmod(r, mulmod(J.w[t], mod_i32(acc[t][i][j][v], J.p, J.pd, J.pinv),
                                                  J.p, J.pinv), J.p);
                     }
-                    uint32_t *cp = J.C + (int64_t)row * J.ldc + col;
-                    if (J.beta) r = addmod(r, mulmod(J.beta, *cp, J.p, J.pinv), J.p);
-                    *cp = r;
+                    if (J.beta) r = addmod(r, mulmod(J.beta, cin[v], J.p, J.pinv), J.p);
+                    J.C[(int64_t)row * J.ldc + col] = r;
                 }
             }
+        }
 }
 
 // Waves per SIMD implied by the workgroup size and the number of resident

@@ -157,7 +157,19 @@ void k_fgemm_i8_pair(I8Job J)
     // Epilogue: lane holds column lane%32 and rows 8*(v/4) + 4*(lane/32) +
     // v%4 of the wave's 32 x 32 block; the recombination modes are those of
     // the plain digit kernel, over the NSET weighted sets.
+    // (C is read for all 16 entries first, clamped into C so that no branch
+    // surrounds the loads: one memory round trip instead of one per entry
+    // behind each store.)
     const int m0 = tm * C::BM + wm0, n0 = tn * C::BN + wn0;
+    uint32_t cin[16];
+    if (J.beta) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = m0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int col = n0 + (lane & 31);
+            cin[v] = J.C[(int64_t)min(row, J.m - 1) * J.ldc + min(col, J.n - 1)];
+        }
+    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int row = m0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -187,9 +199,8 @@ void k_fgemm_i8_pair(I8Job J)
                                          J.pinv),
                                J.p);
             }
-            uint32_t *cp = J.C + (int64_t)row * J.ldc + col;
-            if (J.beta) r = addmod(r, mulmod(J.beta, *cp, J.p, J.pinv), J.p);
-            *cp = r;
+            if (J.beta) r = addmod(r, mulmod(J.beta, cin[v], J.p, J.pinv), J.p);
+            J.C[(int64_t)row * J.ldc + col] = r;
         }
     }
 }
