@@ -141,3 +141,21 @@ def test_trsm_single_block_read_in_place(p):
         ff.ftrsm(p, dT[:, :m], dB, 6, lower, True, unit)
         want = oracle.ftrsm(p, T, B, 6, lower, True, unit)
         assert np.array_equal(from_dev(dB), want), (lower, unit)
+
+
+@pytest.mark.parametrize("p", [7, 65521, 8388593])
+def test_trsm_small_system_many_columns(p):
+    # m <= 64 rows (one diagonal block) with many columns: several leaf
+    # workgroups of columns (the last one ragged), B inside a wider buffer
+    # (ldb = n + 5), every uplo/trans/diag and a non-trivial alpha
+    for si, (m, n) in enumerate([(64, 700), (1, 300), (33, 257), (63, 1)]):
+        T = tri(p, m, 110 + si)
+        B = synth.residues(synth.seed_for(111 + si, 2), (m, n), p)
+        for lower, trans, unit in itertools.product((0, 1), repeat=3):
+            Bw = np.full((m, n + 5), p - 1, np.uint32); Bw[:, :n] = B
+            dT, dB = to_dev(T), to_dev(Bw)
+            ff.ftrsm(p, dT, dB[:, :n], (5 + si) % p, lower, trans, unit)
+            got = from_dev(dB)
+            want = oracle.ftrsm(p, T, B, (5 + si) % p, lower, trans, unit)
+            assert np.array_equal(got[:, :n], want), (m, n, lower, trans, unit)
+            assert np.all(got[:, n:] == p - 1), "wrote outside B"
