@@ -501,7 +501,8 @@ hipError_t run_batched(const I8Job *jobs, int njobs, int total, int persistent,
     X(17, 1, 2, 2, 4, 2, 32, 8, 1, 1) /* 256 x 128, half stages, pipelined */        \
     X(18, 2, 1, 2, 4, 2, 32, 8, 1, 1) /* 128 x 128, half stages, pipelined */        \
     X(19, 1, 2, 4, 4, 2, 64, 8, 0, 1) /* 256 x 256, 8 waves,  128 acc */             \
-    X(20, 1, 2, 2, 2, 2, 64, 4, 1, 2) /* 128 x 128, 4 waves, 2 per CU, pipelined */
+    X(20, 1, 2, 2, 2, 2, 64, 4, 1, 2) /* 128 x 128, 4 waves, 2 per CU, pipelined */  \
+    X(21, 1, 4, 2, 2, 4, 64, 4, 1, 1) /* 256 x 256, 8 waves, 128 acc, pipelined */
 
 namespace {
 const I8Tile k_tiles[] = {

@@ -117,6 +117,16 @@ def test_plan_configs_of_the_workloads():
         assert i.kblock == kb
 
 
+def test_plan_direct_plane_tiles(monkeypatch):
+    # one-digit products: the 256 x 256 tile (id 21) where its tiles fill
+    # whole rounds of one workgroup per CU (256 CUs), else the default two
+    # 128 x 128 workgroups per CU (id 20)
+    monkeypatch.delenv("FF_I8_TILE", raising=False)
+    o = ff.make_opts(path=ff.FF_PATH_INT8, winograd_levels=0)
+    for n, tile in ((2048, 20), (3072, 20), (4096, 21), (6144, 20), (8192, 21)):
+        assert ff.ff_plan_query(251, 0, 0, n, n, n, o).tile_config == tile, n
+
+
 def test_plan_fp64_small_products_need_no_workspace(monkeypatch):
     # m * n <= 512^2 and k <= 768: one launch reads the residues in place
     monkeypatch.delenv("FF_F64_SMALL", raising=False)
