@@ -29,7 +29,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 PER_FILE = {"kernels_f64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
             # the LQUP panel's walk over its 64 rows must unroll completely so
             # that each thread's column stays in registers
-            "kernels_lqup.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+            "kernels_lqup.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"],
+            # likewise the 64-step walk of the diagonal-block inverse, whose
+            # next step's coefficients are requested a step ahead
+            "kernels_trsm.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 
 
 def sources():

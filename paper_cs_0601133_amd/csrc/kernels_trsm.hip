@@ -136,7 +136,10 @@ __device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 // values, exact in binary64 under the bound of the leaf solve (SPLIT: the
 // entries of T' cut in two as there).  Row l, reduced, reaches the four
 // lanes of its column by a DPP quad broadcast (a register move, no LDS
-// round trip): no barrier and no memory access on the 64-step chain.
+// round trip): no barrier and no global memory access on the 64-step chain.
+// With one wave per workgroup nothing hides LDS latency, so each step's
+// coefficients are requested during the step before, and the product that
+// completes the next step's row is issued first.
 //
 // DIRECT (systems of at most 64 rows, whose one leaf reads no T'): the
 // entries come straight from op(T) (InvDirect), restricted to the triangle
@@ -212,10 +215,22 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
         yh[q] = 0.0;
     }
     __syncthreads();
+    // coefficients of a step, requested one step ahead (double-buffered)
+    double cf[2][16], cfh[2][16];
+    auto fetch = [&](int s, double (&c)[16], double (&ch)[16]) {
+        const int l = LOWER ? s : 63 - s;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            c[q] = sT[SPLIT ? 1 : 0][l][rl + 4 * q];
+            if (SPLIT) ch[q] = sT[0][l][rl + 4 * q];
+        }
+    };
+    fetch(0, cf[0], cfh[0]);
 #pragma unroll
     for (int s = 0; s < 64; ++s) {
         const int l = LOWER ? s : 63 - s;
         const int qo = l >> 2, ro = l & 3;
+        if (s + 1 < 64) fetch(s + 1, cf[(s + 1) & 1], cfh[(s + 1) & 1]);
         // every lane reduces its entry q = qo (a value-preserving step); the
         // lane with rl == ro holds row l, now final
         double v = y[qo];
@@ -230,14 +245,16 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
         case 2: yl = quad_bcast<2>(v); break;
         default: yl = quad_bcast<3>(v); break;
         }
+        // the row the next step reduces first
+        const int qn = (LOWER ? (l + 1) : (l - 1 + 64)) % 64 >> 2;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = rl + 4 * q;
+        for (int qq = 0; qq < 16; ++qq) {
+            const int q = (qn + qq) & 15;
             if (SPLIT) {
-                yh[q] = __builtin_fma(-sT[0][l][i], yl, yh[q]);
-                y[q] = __builtin_fma(-sT[SPLIT ? 1 : 0][l][i], yl, y[q]);
+                yh[q] = __builtin_fma(-cfh[s & 1][q], yl, yh[q]);
+                y[q] = __builtin_fma(-cf[s & 1][q], yl, y[q]);
             } else {
-                y[q] = __builtin_fma(-sT[0][l][i], yl, y[q]);
+                y[q] = __builtin_fma(-cf[s & 1][q], yl, y[q]);
             }
         }
     }
