@@ -269,8 +269,9 @@ hipError_t launch_trsm_dinv(const uint32_t *T, int64_t ldt, int64_t m, uint32_t 
 hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower, int64_t m,
                             int64_t ldn, uint32_t p, const uint32_t *dinv, uint32_t *Tn,
                             hipStream_t st);
-// B(i, :) <- alpha dinv_i B(i, :) mod p (dinv null: all ones).
-hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uint32_t p,
+// B(i, :) <- alpha dinv_i B(i, :) mod p (dinv null: all ones); bt: the m x n
+// matrix B is stored transposed (entry (i, j) at B[j ldb + i]).
+hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int bt, int64_t m, int64_t n, uint32_t p,
                              uint32_t alpha, const uint32_t *dinv, hipStream_t st);
 // Tinv[g] = inverse of the 64 x 64 diagonal block g of Tn, g < ldn / 64
 // (64 x 64 row-major each); split as for the leaf.
@@ -285,10 +286,10 @@ hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int
 // Solves rows [r0, r0 + rows) of Tn X = B in place, every other row's
 // contribution already subtracted; r0 a multiple of 64, rows <=
 // TRSM_LEAF_MAX.  split: operands cut in two (needed once
-// 64 (p/2)(p/2 + 2) + p/2 + 2 > 2^53).
+// 64 (p/2)(p/2 + 2) + p/2 + 2 > 2^53).  bt: B (m x n) stored transposed.
 hipError_t launch_trsm_leaf(const uint32_t *Tn, int64_t ldn, const uint32_t *Tinv, int lower,
-                            int64_t r0, int rows, uint32_t *B, int64_t ldb, int64_t m, int64_t n,
-                            uint32_t p, int split, hipStream_t st);
+                            int64_t r0, int rows, uint32_t *B, int64_t ldb, int bt, int64_t m,
+                            int64_t n, uint32_t p, int split, hipStream_t st);
 
 // LQUP (kernels_lqup.hip): rows and window columns of one pivot panel.
 constexpr int LQUP_PANEL = 64;
@@ -310,9 +311,6 @@ hipError_t launch_lqup_identity(uint32_t *Z, int64_t n, hipStream_t st);
 // U[j][c] = A[rows[j]][c0 + c].
 hipError_t launch_lqup_gather(const uint32_t *A, int64_t lda, const int64_t *rows, int64_t r,
                               int64_t c0, int64_t ncols, uint32_t *U, int64_t ldu, hipStream_t st);
-// dst = src^T (src rows x cols).
-hipError_t launch_lqup_transpose(const uint32_t *src, int64_t lds, int64_t rows, int64_t cols,
-                                 uint32_t *dst, int64_t ldd, hipStream_t st);
 // out[r] = first c in [c0, n) with A[i0 + r][c] != 0, or -1, for r < nr.
 hipError_t launch_lqup_first_nonzero(const uint32_t *A, int64_t lda, int64_t i0, int64_t nr,
                                      int64_t c0, int64_t n, int64_t *out, hipStream_t st);

@@ -6,6 +6,13 @@
 
 namespace ff {
 
+// ff_ftrsm_ex with one more choice: bt = 1 takes the m x n matrix B stored
+// transposed (entry (i, j) at B[j * ldb + i], ldb >= m), which is how the
+// LQUP recursion solves G T = X for G in place without transposing X.
+int ftrsm_run(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, uint32_t alpha,
+              const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb, int bt,
+              const ff_opts *opts);
+
 int check_device();
 // Per-(device, stream, slot) device buffer, grown on demand (growth waits
 // for the stream).  Slot 0 serves fgemm; a routine that calls fgemm while

@@ -4,8 +4,7 @@
 // factored by one workgroup (k_lqup_panel), the rest of the work is the
 // triangular solve and the fgemm update of the recursion, plus the column
 // exchanges the pivots require (k_lqup_swap), the gathering of the pivot rows
-// (k_lqup_gather), transposes for the right-hand triangular solve
-// (k_lqup_transpose) and a search for pivots past the panel's window
+// (k_lqup_gather) and a search for pivots past the panel's window
 // (k_lqup_first_nonzero).
 #include "ff_device.h"
 #include "ff_internal.h"
@@ -272,21 +271,6 @@ __global__ __launch_bounds__(256) void k_lqup_gather(const uint32_t *A, int64_t 
         dst[c] = src[c];
 }
 
-// dst[c][r] = src[r][c] for r < rows, c < cols, through 64 x 64 LDS tiles.
-__global__ __launch_bounds__(256) void k_lqup_transpose(const uint32_t *src, int64_t lds,
-                                                        int64_t rows, int64_t cols,
-                                                        uint32_t *dst, int64_t ldd)
-{
-    __shared__ uint32_t tile[64][65];
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int rr = ty; rr < 64; rr += 4)
-        if (r0 + rr < rows && c0 + tx < cols) tile[rr][tx] = src[(r0 + rr) * lds + c0 + tx];
-    __syncthreads();
-    for (int cc = ty; cc < 64; cc += 4)
-        if (c0 + cc < cols && r0 + tx < rows) dst[(c0 + cc) * ldd + r0 + tx] = tile[tx][cc];
-}
-
 // out[r] = first column c in [c0, n) with A[i0 + r][c] != 0, or -1; one
 // workgroup per row.
 __global__ __launch_bounds__(256) void k_lqup_first_nonzero(const uint32_t *A, int64_t lda,
@@ -364,16 +348,6 @@ hipError_t launch_lqup_gather(const uint32_t *A, int64_t lda, const int64_t *row
     const unsigned gx = (unsigned)std::min<int64_t>((ncols + 255) / 256, 64);
     hipLaunchKernelGGL(k_lqup_gather, dim3(gx, (unsigned)r), dim3(256), 0, st, A, lda, rows, r,
                        c0, ncols, U, ldu);
-    return hipGetLastError();
-}
-
-hipError_t launch_lqup_transpose(const uint32_t *src, int64_t lds, int64_t rows, int64_t cols,
-                                 uint32_t *dst, int64_t ldd, hipStream_t st)
-{
-    if (rows <= 0 || cols <= 0) return hipSuccess;
-    if ((rows + 63) / 64 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lqup_transpose, dim3((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64)),
-                       dim3(256), 0, st, src, lds, rows, cols, dst, ldd);
     return hipGetLastError();
 }
 

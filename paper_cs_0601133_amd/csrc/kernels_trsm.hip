@@ -118,6 +118,29 @@ __global__ __launch_bounds__(TT) void k_trsm_scale(uint32_t *B, int64_t ldb, int
     }
 }
 
+// The same for B stored transposed (entry (i, j) at Bt[j ldb + i]): row j of
+// the storage holds column j of B, whose entry i takes the factor of row i.
+__global__ __launch_bounds__(TT) void k_trsm_scale_t(uint32_t *Bt, int64_t ldb, int64_t m,
+                                                     int64_t n, uint32_t p, double pinv,
+                                                     uint32_t alpha, const uint32_t *dinv)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * 4 * TT + threadIdx.x;
+    uint32_t f[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * TT;
+        f[u] = i < m ? (dinv ? mulmod(alpha, dinv[i], p, pinv) : alpha) : 0u;
+    }
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+        uint32_t *row = Bt + j * ldb;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * TT;
+            if (i < m) row[i] = mulmod(f[u], row[i], p, pinv);
+        }
+    }
+}
+
 // x - p rint(x / p) for an integer-valued x, |x| <= 2^53: |result| <= p/2 + 2.
 __device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 {
@@ -372,8 +395,8 @@ __device__ __forceinline__ void settle(v4d &acc, v4d &acc_hi, double pd, double 
 template <bool SPLIT, int NS>
 __global__ __launch_bounds__(LT) void k_trsm_leaf(const uint32_t *Tn, int64_t ldn,
                                                   const uint32_t *Tinv, int lower, int64_t r0,
-                                                  uint32_t *B, int64_t ldb, int64_t m, int64_t n,
-                                                  uint32_t p, double pinv)
+                                                  uint32_t *B, int64_t ldb, int bt, int64_t m,
+                                                  int64_t n, uint32_t p, double pinv)
 {
     __shared__ __attribute__((aligned(16))) double sC[2][OPB]; // residual halves
     __shared__ __attribute__((aligned(16))) double sP[2][OPB]; // halves of X_b
@@ -393,6 +416,8 @@ __global__ __launch_bounds__(LT) void k_trsm_leaf(const uint32_t *Tn, int64_t ld
     uint4 sl[NS > 2 ? NS - 1 : 2][2]; // T' blocks 1.. of the current row
     uint4 si[2][2];                   // inverse block of a row (by parity)
     uint32_t braw[2][4];              // a row's entries of B (by parity; h = 0)
+    // entry (row, this lane's column) of B; bt: B stored transposed
+    auto bidx = [&](int64_t row) { return bt ? gcol * ldb + row : row * ldb + gcol; };
     auto sub = [&](int t) { return lower ? t : NS - 1 - t; };
     auto trow = [&](int t) { return Tn + (r0 + 64 * sub(t) + arow) * ldn + r0 + k0; };
     auto early = [&](int t) {
@@ -400,7 +425,7 @@ __global__ __launch_bounds__(LT) void k_trsm_leaf(const uint32_t *Tn, int64_t ld
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t gr = rb + 16 * g + kg + 4 * r;
-            braw[t & 1][r] = h == 0 && gr < m && colok ? B[gr * ldb + gcol] : 0u;
+            braw[t & 1][r] = h == 0 && gr < m && colok ? B[bidx(gr)] : 0u;
         }
         load_row8(Tinv + (int64_t)4096 * (rb >> 6) + arow * 64 + k0, si[t & 1]);
         if (t > 0) load_row8(trow(t) + 64 * sub(0), s0[t & 1]);
@@ -453,7 +478,7 @@ __global__ __launch_bounds__(LT) void k_trsm_leaf(const uint32_t *Tn, int64_t ld
             const double v = reduce_c(sP[0][e] + sP[1][e], pd, pinv);
             sX[b * OPB + e] = v;
             const int64_t gr = rb + i;
-            if (gr < m && colok) B[gr * ldb + gcol] = canon_f64(v, pd, pinv, p);
+            if (gr < m && colok) B[bidx(gr)] = canon_f64(v, pd, pinv, p);
         }
         __syncthreads();
     }
@@ -461,22 +486,22 @@ __global__ __launch_bounds__(LT) void k_trsm_leaf(const uint32_t *Tn, int64_t ld
 
 template <bool SPLIT, int NS>
 void launch_leaf_ns(dim3 grid, hipStream_t st, const uint32_t *Tn, int64_t ldn,
-                    const uint32_t *Tinv, int lower, int64_t r0, uint32_t *B, int64_t ldb,
+                    const uint32_t *Tinv, int lower, int64_t r0, uint32_t *B, int64_t ldb, int bt,
                     int64_t m, int64_t n, uint32_t p)
 {
     hipLaunchKernelGGL((k_trsm_leaf<SPLIT, NS>), grid, dim3(LT), 0, st, Tn, ldn, Tinv, lower, r0,
-                       B, ldb, m, n, p, 1.0 / (double)p);
+                       B, ldb, bt, m, n, p, 1.0 / (double)p);
 }
 
 template <bool SPLIT>
 void launch_leaf(int ns, dim3 grid, hipStream_t st, const uint32_t *Tn, int64_t ldn,
-                 const uint32_t *Tinv, int lower, int64_t r0, uint32_t *B, int64_t ldb,
+                 const uint32_t *Tinv, int lower, int64_t r0, uint32_t *B, int64_t ldb, int bt,
                  int64_t m, int64_t n, uint32_t p)
 {
     static_assert(NSB == 8, "one instantiation per sub-block count");
     switch (ns) {
 #define FF_LEAF_CASE(k)                                                                        \
-    case k: launch_leaf_ns<SPLIT, k>(grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, m, n, p); break;
+    case k: launch_leaf_ns<SPLIT, k>(grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, bt, m, n, p); break;
         FF_LEAF_CASE(1) FF_LEAF_CASE(2) FF_LEAF_CASE(3) FF_LEAF_CASE(4)
         FF_LEAF_CASE(5) FF_LEAF_CASE(6) FF_LEAF_CASE(7) FF_LEAF_CASE(8)
 #undef FF_LEAF_CASE
@@ -506,9 +531,15 @@ hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower
     return hipGetLastError();
 }
 
-hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uint32_t p,
+hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int bt, int64_t m, int64_t n, uint32_t p,
                              uint32_t alpha, const uint32_t *dinv, hipStream_t st)
 {
+    if (bt) {
+        const dim3 grid((unsigned)((m + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(n, 4096));
+        hipLaunchKernelGGL(k_trsm_scale_t, grid, dim3(TT), 0, st, B, ldb, m, n, p,
+                           1.0 / (double)p, alpha, dinv);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((n + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(m, 4096));
     hipLaunchKernelGGL(k_trsm_scale, grid, dim3(TT), 0, st, B, ldb, m, n, p, 1.0 / (double)p,
                        alpha, dinv);
@@ -557,14 +588,14 @@ hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int
 }
 
 hipError_t launch_trsm_leaf(const uint32_t *Tn, int64_t ldn, const uint32_t *Tinv, int lower,
-                            int64_t r0, int rows, uint32_t *B, int64_t ldb, int64_t m, int64_t n,
-                            uint32_t p, int split, hipStream_t st)
+                            int64_t r0, int rows, uint32_t *B, int64_t ldb, int bt, int64_t m,
+                            int64_t n, uint32_t p, int split, hipStream_t st)
 {
     const int ns = (rows + 63) / 64;
     if (rows < 1 || ns > NSB || r0 % 64) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n + LW - 1) / LW));
-    if (split) launch_leaf<true>(ns, grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, m, n, p);
-    else launch_leaf<false>(ns, grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, m, n, p);
+    if (split) launch_leaf<true>(ns, grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, bt, m, n, p);
+    else launch_leaf<false>(ns, grid, st, Tn, ldn, Tinv, lower, r0, B, ldb, bt, m, n, p);
     return hipGetLastError();
 }
 

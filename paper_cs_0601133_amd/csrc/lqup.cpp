@@ -11,7 +11,8 @@
 // The algorithm is the row recursion the paper describes: factor the top
 // half (pivots T, Y = the rest of their U rows, in the pivot rows), then for
 // the bottom half [X Z] solve G T = X (the right-hand triangular solve, done
-// as T^T G^T = X^T with ftrsm on transposes), update Z <- Z - G Y with one
+// as T^T G^T = X^T by the ftrsm driver reading X as the transposed storage
+// of X^T, so G overwrites X in place), update Z <- Z - G Y with one
 // fgemm, and factor Z.  Blocks of 64 rows are factored by one workgroup
 // over a window of 64 columns (k_lqup_panel); the pivot rows' entries past
 // the window are then finished with a unit lower triangular ftrsm and the
@@ -56,7 +57,6 @@ struct Lqup {
     int32_t *d_fail = nullptr; // set by a panel that contradicts the guess
     // device scratch (workspace slot 2)
     uint32_t *U = nullptr;  // gathered pivot rows
-    uint32_t *Xt = nullptr; // transposed X
     int64_t *d_rows = nullptr, *d_pairs = nullptr, *d_first = nullptr;
     int32_t *d_out = nullptr;
 };
@@ -200,12 +200,11 @@ int rec(Lqup &c, int64_t a, int64_t b, int64_t *found)
             if (rc) return rc;
             FF_HIP_CHECK(launch_lqup_gather(c.A, c.lda, c.d_rows, r1, k0, nc, c.U, nc, c.st));
         }
-        // G T = X  <=>  T^T G^T = X^T
+        // G T = X  <=>  T^T G^T = X^T, solved in place on X read as the
+        // transposed storage of G^T
         uint32_t *X = c.A + mid * c.lda + k0;
-        FF_HIP_CHECK(launch_lqup_transpose(X, c.lda, m2, r1, c.Xt, m2, c.st));
-        rc = ff_ftrsm_ex(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r1, m2, 1, U, ldu, c.Xt, m2, &c.o);
+        rc = ftrsm_run(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r1, m2, 1, U, ldu, X, c.lda, 1, &c.o);
         if (rc) return rc;
-        FF_HIP_CHECK(launch_lqup_transpose(c.Xt, m2, r1, m2, X, c.lda, c.st));
         if (nc > r1) {
             rc = fgemm_sub(c, m2, nc - r1, r1, X, c.lda, U + r1, ldu, X + r1, c.lda);
             if (rc) return rc;
@@ -268,23 +267,22 @@ int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
         if (e != hipSuccess) return fail(FF_EHIP, std::string("validate: ") + hipGetErrorString(e));
         if (h) return fail(FF_EINVAL, std::to_string(h) + " entries of A are not residues < p");
     }
-    // scratch: U (r x n) and X^T (r x m) for r <= min(m, n), row lists,
-    // exchange pairs, panel results
+    // scratch: U (r x n) for r <= min(m, n), row lists, exchange pairs,
+    // panel results
     const int64_t rmax = std::min(m, n);
-    const int64_t u_bytes = round_up(rmax * n * 4, 256), x_bytes = round_up(rmax * m * 4, 256);
+    const int64_t u_bytes = round_up(rmax * n * 4, 256);
     const int64_t rows_bytes = round_up(m * 8, 256), pairs_bytes = round_up(2 * std::max<int64_t>(n, 64) * 8, 256);
     const int64_t out_bytes = 1024, first_bytes = round_up(LQUP_PANEL * 8, 256);
     void *ws = nullptr;
-    rc = workspace(c.st, (size_t)(u_bytes + x_bytes + rows_bytes + pairs_bytes + out_bytes + first_bytes),
+    rc = workspace(c.st, (size_t)(u_bytes + rows_bytes + pairs_bytes + out_bytes + first_bytes),
                    &ws, 2);
     if (rc) return rc;
     char *w = (char *)ws;
     c.U = (uint32_t *)w;
-    c.Xt = (uint32_t *)(w + u_bytes);
-    c.d_rows = (int64_t *)(w + u_bytes + x_bytes);
-    c.d_pairs = (int64_t *)(w + u_bytes + x_bytes + rows_bytes);
-    c.d_out = (int32_t *)(w + u_bytes + x_bytes + rows_bytes + pairs_bytes);
-    c.d_first = (int64_t *)(w + u_bytes + x_bytes + rows_bytes + pairs_bytes + out_bytes);
+    c.d_rows = (int64_t *)(w + u_bytes);
+    c.d_pairs = (int64_t *)(w + u_bytes + rows_bytes);
+    c.d_out = (int32_t *)(w + u_bytes + rows_bytes + pairs_bytes);
+    c.d_first = (int64_t *)(w + u_bytes + rows_bytes + pairs_bytes + out_bytes);
     c.d_fail = (int32_t *)(c.d_out + 3 + 2 * LQUP_PANEL);
     int64_t found = 0;
     bool guessed = false;

@@ -49,6 +49,7 @@ struct Trsm {
     const uint32_t *Tinv; // ldn / 64 blocks of 64 x 64
     uint32_t *B;
     int64_t ldb;
+    int bt; // B stored transposed (entry (i, j) at B[j * ldb + i])
     int64_t leaf;
     int split;
     ff_opts o; // inner fgemm options (stream set, no validation)
@@ -61,41 +62,40 @@ int solve(const Trsm &c, int64_t r0, int64_t r1)
     if (size <= c.leaf) {
         FF_HIP_CHECK(FF_TIMED(PROF_SLICE, c.st,
                               launch_trsm_leaf(c.Tn, c.ldn, c.Tinv, c.lower, r0, (int)size, c.B,
-                                               c.ldb, c.m, c.n, c.p, c.split, c.st)));
+                                               c.ldb, c.bt, c.m, c.n, c.p, c.split, c.st)));
         return FF_OK;
     }
     // split at a multiple of 64 near the middle
     const int64_t mid = r0 + round_up(size / 2, 64);
     const uint32_t minus1 = c.p - 1;
+    // rows [d0, d1) of B -= T'[d0:d1, s0:s1] X[s0:s1]; with B stored
+    // transposed the same update reads Bt[:, d0:d1] -= Bt[:, s0:s1] T'[d0:d1, s0:s1]^T
+    auto update = [&](int64_t d0, int64_t d1, int64_t s0, int64_t s1) {
+        const uint32_t *Tb = c.Tn + d0 * c.ldn + s0;
+        if (c.bt)
+            return ff_fgemm_ex(c.p, 0, 1, c.n, d1 - d0, s1 - s0, minus1, c.B + s0, c.ldb, Tb,
+                               c.ldn, 1, c.B + d0, c.ldb, &c.o);
+        return ff_fgemm_ex(c.p, 0, 0, d1 - d0, c.n, s1 - s0, minus1, Tb, c.ldn, c.B + s0 * c.ldb,
+                           c.ldb, 1, c.B + d0 * c.ldb, c.ldb, &c.o);
+    };
     int rc;
     if (!c.lower) {
         // upper: rows [mid, r1) first, then B[r0:mid] -= T'[r0:mid, mid:r1] X[mid:r1]
         if ((rc = solve(c, mid, r1))) return rc;
-        if ((rc = ff_fgemm_ex(c.p, 0, 0, mid - r0, c.n, r1 - mid, minus1,
-                              c.Tn + r0 * c.ldn + mid, c.ldn, c.B + mid * c.ldb, c.ldb, 1,
-                              c.B + r0 * c.ldb, c.ldb, &c.o)))
-            return rc;
+        if ((rc = update(r0, mid, mid, r1))) return rc;
         return solve(c, r0, mid);
     }
     // lower: rows [r0, mid) first, then B[mid:r1] -= T'[mid:r1, r0:mid] X[r0:mid]
     if ((rc = solve(c, r0, mid))) return rc;
-    if ((rc = ff_fgemm_ex(c.p, 0, 0, r1 - mid, c.n, mid - r0, minus1, c.Tn + mid * c.ldn + r0,
-                          c.ldn, c.B + r0 * c.ldb, c.ldb, 1, c.B + mid * c.ldb, c.ldb, &c.o)))
-        return rc;
+    if ((rc = update(mid, r1, r0, mid))) return rc;
     return solve(c, mid, r1);
 }
 
 } // namespace
 
-} // namespace ff
-
-using namespace ff;
-
-extern "C" {
-
-int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n,
-                uint32_t alpha, const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb,
-                const ff_opts *opts)
+int ftrsm_run(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, uint32_t alpha,
+              const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb, int bt,
+              const ff_opts *opts)
 {
     if (p < 2 || p > 0x7FFFFFFFu) return fail(FF_EINVAL, "p must be in [2, 2^31 - 1]");
     if ((uplo != FF_UPPER && uplo != FF_LOWER) || (transT != FF_NOTRANS && transT != FF_TRANS) ||
@@ -106,7 +106,7 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
     if (m == 0 || n == 0) return FF_OK;
     if (!T || !B) return fail(FF_EINVAL, "null matrix pointer");
     if (ldt < m) return fail(FF_EINVAL, "ldt < m");
-    if (ldb < n) return fail(FF_EINVAL, "ldb < n");
+    if (ldb < (bt ? m : n)) return fail(FF_EINVAL, bt ? "ldb < m" : "ldb < n");
     if (m > 0x7FFFFFFF / 2) return fail(FF_EINVAL, "m too large");
     ff_opts o = opts ? *opts : default_opts();
     int rc = check_device();
@@ -118,7 +118,7 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
         FF_HIP_CHECK(hipMalloc(&bad, sizeof(unsigned)));
         unsigned h = 0;
         hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned), st);
-        if (e == hipSuccess) e = launch_validate(B, ldb, m, n, p, bad, st);
+        if (e == hipSuccess) e = launch_validate(B, ldb, bt ? n : m, bt ? m : n, p, bad, st);
         if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         (void)hipFree(bad);
@@ -126,7 +126,7 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
         if (h) return fail(FF_EINVAL, std::to_string(h) + " entries of B are not residues < p");
     }
     if (alpha == 0) { // X = 0
-        FF_HIP_CHECK(launch_scale(B, ldb, m, n, p, 0, st));
+        FF_HIP_CHECK(launch_scale(B, ldb, bt ? n : m, bt ? m : n, p, 0, st));
         return FF_OK;
     }
     // workspace slot 1 (the inner fgemm calls use slot 0): T', the inverses
@@ -170,7 +170,7 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
         FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, ldn, p, dv, Tn, st));
         FF_HIP_CHECK(launch_trsm_inv(Tn, ldn, lower, p, split, Tinv, st));
     }
-    if (alpha != 1 || !unit) FF_HIP_CHECK(launch_trsm_scale(B, ldb, m, n, p, alpha, dv, st));
+    if (alpha != 1 || !unit) FF_HIP_CHECK(launch_trsm_scale(B, ldb, bt, m, n, p, alpha, dv, st));
     Trsm c;
     c.p = p;
     c.lower = lower;
@@ -181,6 +181,7 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
     c.Tinv = Tinv;
     c.B = B;
     c.ldb = ldb;
+    c.bt = bt;
     c.leaf = trsm_leaf_rows();
     c.split = split;
     c.o = o;
@@ -188,6 +189,19 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
     c.o.validate = 0;
     c.st = st;
     return solve(c, 0, m);
+}
+
+} // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n,
+                uint32_t alpha, const uint32_t *T, int64_t ldt, uint32_t *B, int64_t ldb,
+                const ff_opts *opts)
+{
+    return ftrsm_run(p, uplo, transT, diag, m, n, alpha, T, ldt, B, ldb, 0, opts);
 }
 
 int ff_ftrsm(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, uint32_t alpha,
