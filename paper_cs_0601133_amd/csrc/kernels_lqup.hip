@@ -26,11 +26,15 @@ __device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 }
 
 // Inverse of a unit a modulo p (extended Euclid); 0 if a is not a unit.
+// Remainders stay below p < 2^31 (32-bit division steps); the Bezout
+// coefficients need 64 bits.
 __device__ __forceinline__ uint32_t inv_mod(uint32_t a, uint32_t p)
 {
-    int64_t r0 = p, r1 = a % p, s0 = 0, s1 = 1;
+    uint32_t r0 = p, r1 = a % p;
+    int64_t s0 = 0, s1 = 1;
     while (r1 != 0) {
-        const int64_t q = r0 / r1, r2 = r0 - q * r1, s2 = s0 - q * s1;
+        const uint32_t q = r0 / r1, r2 = r0 - q * r1;
+        const int64_t s2 = s0 - (int64_t)q * s1;
         r0 = r1; r1 = r2; s0 = s1; s1 = s2;
     }
     if (r0 != 1) return 0;

@@ -27,13 +27,16 @@ __device__ __forceinline__ uint32_t op_t(const uint32_t *T, int64_t ldt, int tra
     return trans ? T[j * ldt + i] : T[i * ldt + j];
 }
 
-// Inverse of a modulo p by the extended Euclidean algorithm; 0 when a is
-// not a unit (gcd(a, p) != 1).
-__device__ __forceinline__ uint32_t inv_mod(uint32_t a, uint32_t p)
+// Inverse of a modulo p by the extended Euclidean algorithm, 0 when a is
+// not a unit (gcd(a, p) != 1).  Remainders stay below p < 2^31, so each
+// division step is a 32-bit one; the Bezout coefficients need 64 bits.
+__device__ __forceinline__ uint32_t inv_mod32(uint32_t a, uint32_t p)
 {
-    int64_t r0 = p, r1 = a % p, s0 = 0, s1 = 1;
+    uint32_t r0 = p, r1 = a % p;
+    int64_t s0 = 0, s1 = 1;
     while (r1 != 0) {
-        const int64_t q = r0 / r1, r2 = r0 - q * r1, s2 = s0 - q * s1;
+        const uint32_t q = r0 / r1, r2 = r0 - q * r1;
+        const int64_t s2 = s0 - (int64_t)q * s1;
         r0 = r1; r1 = r2; s0 = s1; s1 = s2;
     }
     if (r0 != 1) return 0;
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(TT) void k_trsm_dinv(const uint32_t *T, int64_t ldt
     if (i >= m) return;
     uint32_t d = 1;
     if (!unit) {
-        d = inv_mod(T[i * ldt + i], p);
+        d = inv_mod32(T[i * ldt + i], p);
         if (d == 0 && bad) atomicAdd(bad, 1u);
     }
     dinv[i] = d;
@@ -137,6 +140,80 @@ __global__ __launch_bounds__(TT) void k_trsm_scale_t(uint32_t *Bt, int64_t ldb, 
         for (int u = 0; u < 4; ++u) {
             const int64_t i = i0 + u * TT;
             if (i < m) row[i] = mulmod(f[u], row[i], p, pinv);
+        }
+    }
+}
+
+// B(i, j) <- alpha dinv_i B(i, j) with dinv_i the inverse of T(i, i) taken
+// here (unit: none), in one pass: every workgroup inverts the diagonal
+// entries of the rows it scales, and one column of workgroups also writes
+// them to dinv_out (null: not wanted) for the kernels that normalise T.
+// BT: B stored transposed (entry (i, j) at B[j ldb + i]).  Workgroup (x, y):
+// BT: rows i in [1024 x, 1024 x + 1024), storage rows j = y, y + gridDim.y, ..;
+// else: columns [1024 x, 1024 x + 1024), rows i = y, y + gridDim.y, ...
+// gridDim.y is kept small (64): it is the number of times each inverse is
+// taken.
+template <bool BT>
+__global__ __launch_bounds__(TT) void k_trsm_dscale(const uint32_t *T, int64_t ldt, int unit,
+                                                    uint32_t *B, int64_t ldb, int64_t m,
+                                                    int64_t n, uint32_t p, double pinv,
+                                                    uint32_t alpha, uint32_t *dinv_out)
+{
+    auto factor = [&](int64_t i, bool write) {
+        if (unit) return alpha;
+        const uint32_t d = inv_mod32(T[i * ldt + i], p);
+        if (write && dinv_out) dinv_out[i] = d;
+        return mulmod(alpha, d, p, pinv);
+    };
+    if (BT) {
+        const int64_t i0 = (int64_t)blockIdx.x * 4 * TT + threadIdx.x;
+        uint32_t f[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * TT;
+            f[u] = i < m ? factor(i, blockIdx.y == 0) : 0u;
+        }
+        // four storage rows at a time, all loads before the stores (a load
+        // after a store to B would wait for it: the addresses may alias)
+        const int64_t G = gridDim.y;
+        for (int64_t j = blockIdx.y; j < n; j += 4 * G) {
+            uint32_t v[4][4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t i = i0 + u * TT, jj = j + b * G;
+                    v[b][u] = i < m && jj < n ? B[jj * ldb + i] : 0u;
+                }
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t i = i0 + u * TT, jj = j + b * G;
+                    if (i < m && jj < n) B[jj * ldb + i] = mulmod(f[u], v[b][u], p, pinv);
+                }
+        }
+    } else {
+        // the workgroup's rows i = y + k gridDim.y, their factors taken TT
+        // at a time (one inversion per thread) and shared through LDS
+        __shared__ uint32_t sf[TT];
+        const int64_t j0 = (int64_t)blockIdx.x * 4 * TT + threadIdx.x;
+        const int64_t nk = (m - blockIdx.y + gridDim.y - 1) / gridDim.y;
+        for (int64_t k0 = 0; k0 < nk; k0 += TT) {
+            const int64_t kk = k0 + threadIdx.x;
+            if (kk < nk) sf[threadIdx.x] = factor(blockIdx.y + kk * gridDim.y, blockIdx.x == 0);
+            __syncthreads();
+            const int64_t kend = nk - k0 < TT ? nk - k0 : TT;
+            for (int64_t q = 0; q < kend; ++q) {
+                const uint32_t f = sf[q];
+                uint32_t *row = B + (blockIdx.y + (k0 + q) * gridDim.y) * ldb;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t j = j0 + u * TT;
+                    if (j < n) row[j] = mulmod(f, row[j], p, pinv);
+                }
+            }
+            __syncthreads();
         }
     }
 }
@@ -584,6 +661,24 @@ hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int
     if (m < 1 || m > 64) return hipErrorInvalidValue;
     launch_inv<true>(dim3(4), st, nullptr, 0, lower, p, split, Tinv,
                      InvDirect{T, ldt, trans, (int)m, dinv});
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_dscale(const uint32_t *T, int64_t ldt, int unit, uint32_t *B,
+                              int64_t ldb, int bt, int64_t m, int64_t n, uint32_t p,
+                              uint32_t alpha, uint32_t *dinv_out, hipStream_t st)
+{
+    const double pinv = 1.0 / (double)p;
+    if (bt) {
+        // few workgroup rows: each one inverts its 1024 diagonal entries
+        const dim3 grid((unsigned)((m + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(n, 64));
+        hipLaunchKernelGGL(k_trsm_dscale<true>, grid, dim3(TT), 0, st, T, ldt, unit, B, ldb, m,
+                           n, p, pinv, alpha, dinv_out);
+    } else {
+        const dim3 grid((unsigned)((n + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(m, 64));
+        hipLaunchKernelGGL(k_trsm_dscale<false>, grid, dim3(TT), 0, st, T, ldt, unit, B, ldb, m,
+                           n, p, pinv, alpha, dinv_out);
+    }
     return hipGetLastError();
 }
 

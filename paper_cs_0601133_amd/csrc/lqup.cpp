@@ -29,12 +29,16 @@
 // exchange), which fixes every size in advance: nothing is read back per
 // panel, the pivot rows of a half are its rows in place (no gather), and
 // each panel kernel records in a device flag whether the guess held for it.
+// Each panel's solve for its pivot rows past the window runs on a second
+// stream, beside the right-hand solve that follows it (see Aux).
 // The flag is read once at the end; if any panel saw otherwise, A is
 // restored from a copy taken at the start and the factorisation runs again
 // with the read-backs above.  Either way the result is the same unique
 // factorisation.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "ff_runtime.h"
@@ -42,6 +46,55 @@
 namespace ff {
 
 namespace {
+
+// A second stream and two events, borrowed per factorisation from a pool
+// per device: on the fast path each panel's solve for its pivot rows past
+// the window runs there, beside the next right-hand solve (which does not
+// read those entries); the main stream waits for it before the update that
+// does.  Both are latency-bound launches of a few workgroups.
+struct Aux {
+    hipStream_t st = nullptr;
+    hipEvent_t panel = nullptr, y = nullptr;
+};
+
+std::mutex g_aux_mu;
+std::map<int, std::vector<Aux>> g_aux_free;
+
+bool aux_acquire(Aux *a)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    {
+        std::lock_guard<std::mutex> lk(g_aux_mu);
+        std::vector<Aux> &v = g_aux_free[dev];
+        if (!v.empty()) {
+            *a = v.back();
+            v.pop_back();
+            return true;
+        }
+    }
+    Aux n;
+    bool ok = hipStreamCreateWithFlags(&n.st, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&n.panel, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&n.y, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        if (n.y) (void)hipEventDestroy(n.y);
+        if (n.panel) (void)hipEventDestroy(n.panel);
+        if (n.st) (void)hipStreamDestroy(n.st);
+        return false;
+    }
+    *a = n;
+    return true;
+}
+
+void aux_release(const Aux &a)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    g_aux_free[dev].push_back(a);
+}
 
 struct Lqup {
     uint32_t p;
@@ -55,6 +108,9 @@ struct Lqup {
     std::vector<int64_t> colperm;
     bool spec = false;      // full-rank guess in force (see above)
     int32_t *d_fail = nullptr; // set by a panel that contradicts the guess
+    Aux aux;                // second stream (fast path), if one was had
+    bool have_aux = false;
+    bool y_pending = false; // a panel's solve past its window still runs on aux.st
     // device scratch (workspace slot 2)
     uint32_t *U = nullptr;  // gathered pivot rows
     int64_t *d_rows = nullptr, *d_pairs = nullptr, *d_first = nullptr;
@@ -82,6 +138,15 @@ int exchange(Lqup &c, const std::vector<int64_t> &pairs, int64_t skip_lo, int64_
     return FF_OK;
 }
 
+// The main stream waits for the last panel's solve on the second stream.
+int wait_y(Lqup &c)
+{
+    if (!c.y_pending) return FF_OK;
+    FF_HIP_CHECK(hipStreamWaitEvent(c.st, c.aux.y, 0));
+    c.y_pending = false;
+    return FF_OK;
+}
+
 // Fast-path panel: rows [a, b) assumed to be pivot rows in columns
 // [c.k, c.k + b - a) in order; the kernel flags the guess if it fails.
 int panel_guess(Lqup &c, int64_t a, int64_t b, int64_t *found)
@@ -94,9 +159,19 @@ int panel_guess(Lqup &c, int64_t a, int64_t b, int64_t *found)
     if (!whole && nr <= W) {
         const int64_t nc = c.n - c.k - W;
         uint32_t *T = c.A + a * c.lda + c.k;
+        ff_opts o = c.o;
+        if (c.have_aux) {
+            FF_HIP_CHECK(hipEventRecord(c.aux.panel, c.st));
+            FF_HIP_CHECK(hipStreamWaitEvent(c.aux.st, c.aux.panel, 0));
+            o.stream = (void *)c.aux.st;
+        }
         int rc = ff_ftrsm_ex(c.p, FF_LOWER, FF_NOTRANS, FF_UNIT, nr, nc, 1, T, c.lda,
-                             c.A + a * c.lda + c.k + W, c.lda, &c.o);
+                             c.A + a * c.lda + c.k + W, c.lda, &o);
         if (rc) return rc;
+        if (c.have_aux) {
+            FF_HIP_CHECK(hipEventRecord(c.aux.y, c.aux.st));
+            c.y_pending = true;
+        }
     }
     for (int64_t r = a; r < b; ++r) c.piv.push_back(r);
     c.k += nr;
@@ -205,11 +280,14 @@ int rec(Lqup &c, int64_t a, int64_t b, int64_t *found)
         uint32_t *X = c.A + mid * c.lda + k0;
         rc = ftrsm_run(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r1, m2, 1, U, ldu, X, c.lda, 1, &c.o);
         if (rc) return rc;
+        // Y's last columns may still be in the making on the second stream
+        if ((rc = wait_y(c))) return rc;
         if (nc > r1) {
             rc = fgemm_sub(c, m2, nc - r1, r1, X, c.lda, U + r1, ldu, X + r1, c.lda);
             if (rc) return rc;
         }
     }
+    if ((rc = wait_y(c))) return rc;
     rc = rec(c, mid, b, &r2);
     if (rc) return rc;
     *found = r1 + r2;
@@ -243,6 +321,17 @@ int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
     int rc = check_device();
     if (rc) return rc;
     Lqup c;
+    // on every return: the second stream's work is done and it goes back to
+    // the pool
+    struct AuxGuard {
+        Lqup &c;
+        ~AuxGuard()
+        {
+            if (!c.have_aux) return;
+            (void)hipStreamSynchronize(c.aux.st);
+            aux_release(c.aux);
+        }
+    } aux_guard{c};
     c.p = p;
     c.m = m;
     c.n = n;
@@ -294,8 +383,10 @@ int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
                                       (size_t)m, hipMemcpyDeviceToDevice, c.st));
         FF_HIP_CHECK(launch_scale((uint32_t *)c.d_fail, 1, 1, 1, 2u, 0u, c.st));
         c.spec = true;
+        c.have_aux = aux_acquire(&c.aux); // else everything stays on c.st
         rc = rec(c, 0, m, &found);
         if (rc) return rc;
+        if ((rc = wait_y(c))) return rc;
         int32_t failed = 1;
         FF_HIP_CHECK(hipMemcpyAsync(&failed, c.d_fail, sizeof(failed), hipMemcpyDeviceToHost,
                                     c.st));

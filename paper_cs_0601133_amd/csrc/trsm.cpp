@@ -141,10 +141,18 @@ int ftrsm_run(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, 
     uint32_t *dinv = (uint32_t *)((char *)wsv + tn_bytes + ti_bytes);
     unsigned *bad = (unsigned *)((char *)wsv + tn_bytes + ti_bytes + di_bytes);
     const int lower = (uplo == FF_LOWER) ^ (transT == FF_TRANS);
-    // a unit diagonal needs no inverses (dinv stays null for the kernels);
-    // the flag that counts non-invertible entries is only read by validate
+    // a unit diagonal needs no inverses (dinv stays null for the kernels).
+    // B stored transposed (the LQUP recursion's right-hand solves) and
+    // systems of at most 64 rows take the inverses in the pass that scales
+    // B (one launch instead of two); larger row-major systems, and any
+    // solve that validates (it counts the entries without an inverse), take
+    // them in a pass of their own, one thread per row, and scale B after.
     const bool unit = diag == FF_UNIT;
-    if (!unit) {
+    const bool fused = !o.validate && (bt || m <= 64);
+    if (fused && (alpha != 1 || !unit))
+        FF_HIP_CHECK(launch_trsm_dscale(T, ldt, unit, B, ldb, bt, m, n, p, alpha,
+                                        unit ? nullptr : dinv, st));
+    if (!unit && !fused) {
         if (o.validate) FF_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), st));
         FF_HIP_CHECK(launch_trsm_dinv(T, ldt, m, p, 0, dinv, o.validate ? bad : nullptr, st));
         if (o.validate) {
@@ -170,7 +178,8 @@ int ftrsm_run(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, 
         FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, ldn, p, dv, Tn, st));
         FF_HIP_CHECK(launch_trsm_inv(Tn, ldn, lower, p, split, Tinv, st));
     }
-    if (alpha != 1 || !unit) FF_HIP_CHECK(launch_trsm_scale(B, ldb, bt, m, n, p, alpha, dv, st));
+    if (!fused && (alpha != 1 || !unit))
+        FF_HIP_CHECK(launch_trsm_scale(B, ldb, bt, m, n, p, alpha, dv, st));
     Trsm c;
     c.p = p;
     c.lower = lower;
