@@ -543,6 +543,14 @@ def serving(torch, ff, args):
     total_ops = sum(r[2] for r in reqs)
     budget = 24 << 30
     out = {"requests": nreq, "sum_2mnk": total_ops, "hbm_budget_bytes": budget}
+    # untimed pass of the same stream first (first launches of the batched
+    # kernels, workspace and arena growth), as every other workload settles
+    # before it is timed
+    srv = ff.ff_server_create(budget)
+    ids = [ff.ff_server_submit(srv, r[0]) for r in reqs]
+    for i in ids:
+        ff.ff_server_wait(srv, i)
+    ff.ff_server_destroy(srv)
     # closed loop: everything submitted at once -> capacity
     srv = ff.ff_server_create(budget)
     t0 = time.perf_counter()
@@ -576,12 +584,13 @@ def serving(torch, ff, args):
                                   "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                                   "max_inflight": st["max_inflight"]}
         log(f"serve poisson {load}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms")
-    # every request's result after the three runs (C <- 3AB + 5C applied
-    # three times), by Freivalds against its initial C
+    # every request's result after the four runs (C <- 3AB + 5C applied
+    # four times: the untimed pass, the closed loop and two Poisson
+    # streams), by Freivalds against its initial C
     torch.cuda.synchronize()
     good = 0
     for i, (_, (dA, dB, dC, dC0, p), _) in enumerate(reqs):
-        a_T, b_T = repeated_coeffs(3, 3, 5, p)
+        a_T, b_T = repeated_coeffs(4, 3, 5, p)
         host = [t.cpu().numpy().view(np.uint32) for t in (dA, dB, dC0, dC)]
         good += freivalds_check(host[0], host[1], host[2], host[3], a_T, b_T, p, 1, 1000 + i)
     out["check"] = {"kind": "freivalds", "trials": 1, "requests": nreq, "ok": int(good)}
