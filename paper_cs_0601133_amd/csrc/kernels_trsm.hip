@@ -8,6 +8,7 @@
 // (at most TRSM_LEAF_MAX rows) for a strip of 16 columns of B; the updates
 // between leaves are fgemm calls (trsm.cpp).
 #include <algorithm>
+#include <utility>
 
 #include "ff_device.h"
 #include "ff_internal.h"
@@ -230,14 +231,16 @@ __device__ __forceinline__ double reduce_c(double x, double pd, double pinv)
 // upper: l = 63, 62, ..) y_l is final once the rows before it have been
 // subtracted, and is then subtracted, times T'(i, l), from every other row
 // (T' is read with its diagonal set to 0, and it is 0 on the far side of the
-// triangle, so no row needs a test).  One wave takes 16 columns of one
-// block; lane 4 jl + rl keeps rows rl + 4q, q < 16, of column 16 jq + jl in
-// registers, unreduced: each is a sum of at most 63 products of centered
-// values, exact in binary64 under the bound of the leaf solve (SPLIT: the
-// entries of T' cut in two as there).  Row l, reduced, reaches the four
-// lanes of its column by a DPP quad broadcast (a register move, no LDS
-// round trip): no barrier and no global memory access on the 64-step chain.
-// With one wave per workgroup nothing hides LDS latency, so each step's
+// triangle, so no row needs a test).  One wave takes 4 columns of one
+// block (16 workgroups per block); lane 16 jl + rl keeps rows rl + 16q,
+// q < 4, of column 4 jq + jl in registers, unreduced: each is a sum of at
+// most 63 products of centered values, exact in binary64 under the bound of
+// the leaf solve (SPLIT: the entries of T' cut in two as there).  Row l,
+// reduced, reaches the 16 lanes of its column by a DPP row broadcast (a
+// register move, no LDS round trip): no barrier and no global memory access
+// on the 64-step chain, and 4 products per lane and step (with 4 lanes per
+// column and 16 products per step the chain took 14.6 us per block).  With
+// one wave per workgroup nothing hides LDS latency, so each step's
 // coefficients are requested during the step before, and the product that
 // completes the next step's row is issued first.
 //
@@ -252,14 +255,30 @@ struct InvDirect {
     const uint32_t *dinv; // null: unit diagonal
 };
 
-// v of lane 4 (lane / 4) + R, to every lane of its quad.
+// Lanes per column of the inverse: lane LPC jl + rl keeps rows rl + LPC q
+// (q < NQ) of one column, so each of the 64 steps costs NQ products per lane.
+constexpr int LPC = 16;
+constexpr int NQ = 64 / LPC;
+constexpr int WPB = LPC; // workgroups (one wave, 64 / LPC columns each) per block
+
+// v of lane LPC (lane / LPC) + R, to every lane of its group of LPC (a DPP
+// row broadcast: the groups are the 16-lane rows).
 template <int R>
-__device__ __forceinline__ double quad_bcast(double v)
+__device__ __forceinline__ double group_bcast(double v)
 {
-    constexpr int ctrl = R | (R << 2) | (R << 4) | (R << 6); // quad_perm [R, R, R, R]
+    static_assert(LPC == 16, "one DPP row per column");
+    constexpr int ctrl = 0x150 | R; // row_newbcast:R
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
+}
+
+template <int... R>
+__device__ __forceinline__ double group_bcast_rt(double v, int r, std::integer_sequence<int, R...>)
+{
+    double out = 0.0;
+    ((r == R ? (void)(out = group_bcast<R>(v)) : (void)0), ...);
+    return out;
 }
 
 template <bool SPLIT, bool LOWER, bool DIRECT>
@@ -269,9 +288,9 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
     // sT[.][l][i] = T'(i, l), diagonal 0; rows padded to 65 so that the
     // transposing stores (one l per lane) spread over the banks
     __shared__ double sT[SPLIT ? 2 : 1][64][65];
-    const int g = blockIdx.x >> 2, jq = blockIdx.x & 3;
-    const int lane = threadIdx.x, jl = lane >> 2, rl = lane & 3;
-    const int j = 16 * jq + jl;
+    const int g = blockIdx.x / WPB, jq = blockIdx.x % WPB;
+    const int lane = threadIdx.x, jl = lane / LPC, rl = lane % LPC;
+    const int j = (64 / LPC) * jq + jl;
     const uint32_t half = (p - 1) / 2;
     const double pd = (double)p;
     uint32_t raw[64]; // row i, column l = lane: all loads in flight at once
@@ -308,28 +327,28 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
             sT[0][col][row] = t;
         }
     }
-    double y[16], yh[16];
+    double y[NQ], yh[NQ];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        y[q] = rl + 4 * q == j ? 1.0 : 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        y[q] = rl + LPC * q == j ? 1.0 : 0.0;
         yh[q] = 0.0;
     }
     __syncthreads();
     // coefficients of a step, requested one step ahead (double-buffered)
-    double cf[2][16], cfh[2][16];
-    auto fetch = [&](int s, double (&c)[16], double (&ch)[16]) {
+    double cf[2][NQ], cfh[2][NQ];
+    auto fetch = [&](int s, double (&c)[NQ], double (&ch)[NQ]) {
         const int l = LOWER ? s : 63 - s;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            c[q] = sT[SPLIT ? 1 : 0][l][rl + 4 * q];
-            if (SPLIT) ch[q] = sT[0][l][rl + 4 * q];
+        for (int q = 0; q < NQ; ++q) {
+            c[q] = sT[SPLIT ? 1 : 0][l][rl + LPC * q];
+            if (SPLIT) ch[q] = sT[0][l][rl + LPC * q];
         }
     };
     fetch(0, cf[0], cfh[0]);
 #pragma unroll
     for (int s = 0; s < 64; ++s) {
         const int l = LOWER ? s : 63 - s;
-        const int qo = l >> 2, ro = l & 3;
+        const int qo = l / LPC, ro = l % LPC;
         if (s + 1 < 64) fetch(s + 1, cf[(s + 1) & 1], cfh[(s + 1) & 1]);
         // every lane reduces its entry q = qo (a value-preserving step); the
         // lane with rl == ro holds row l, now final
@@ -338,18 +357,13 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
         v = reduce_c(v, pd, pinv);
         y[qo] = v;
         yh[qo] = 0.0;
-        double yl;
-        switch (ro) { // a constant once the loop is unrolled
-        case 0: yl = quad_bcast<0>(v); break;
-        case 1: yl = quad_bcast<1>(v); break;
-        case 2: yl = quad_bcast<2>(v); break;
-        default: yl = quad_bcast<3>(v); break;
-        }
+        // ro is a constant once the loop is unrolled
+        const double yl = group_bcast_rt(v, ro, std::make_integer_sequence<int, LPC>{});
         // the row the next step reduces first
-        const int qn = (LOWER ? (l + 1) : (l - 1 + 64)) % 64 >> 2;
+        const int qn = ((LOWER ? (l + 1) : (l - 1 + 64)) % 64) / LPC;
 #pragma unroll
-        for (int qq = 0; qq < 16; ++qq) {
-            const int q = (qn + qq) & 15;
+        for (int qq = 0; qq < NQ; ++qq) {
+            const int q = (qn + qq) % NQ;
             if (SPLIT) {
                 yh[q] = __builtin_fma(-cfh[s & 1][q], yl, yh[q]);
                 y[q] = __builtin_fma(-cf[s & 1][q], yl, y[q]);
@@ -362,7 +376,7 @@ __global__ __launch_bounds__(64) void k_trsm_inv(const uint32_t *Tn, int64_t ldn
     // T'(i, l) = 0 terms only)
     uint32_t *dst = Tinv + (int64_t)4096 * g;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) dst[(rl + 4 * q) * 64 + j] = canon_f64(y[q], pd, pinv, p);
+    for (int q = 0; q < NQ; ++q) dst[(rl + LPC * q) * 64 + j] = canon_f64(y[q], pd, pinv, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -649,7 +663,7 @@ void launch_inv(dim3 grid, hipStream_t st, const uint32_t *Tn, int64_t ldn, int 
 hipError_t launch_trsm_inv(const uint32_t *Tn, int64_t ldn, int lower, uint32_t p, int split,
                            uint32_t *Tinv, hipStream_t st)
 {
-    launch_inv<false>(dim3((unsigned)(ldn / 64 * 4)), st, Tn, ldn, lower, p, split, Tinv,
+    launch_inv<false>(dim3((unsigned)(ldn / 64 * WPB)), st, Tn, ldn, lower, p, split, Tinv,
                       InvDirect{nullptr, 0, 0, 0, nullptr});
     return hipGetLastError();
 }
@@ -659,7 +673,7 @@ hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int
                                   uint32_t *Tinv, hipStream_t st)
 {
     if (m < 1 || m > 64) return hipErrorInvalidValue;
-    launch_inv<true>(dim3(4), st, nullptr, 0, lower, p, split, Tinv,
+    launch_inv<true>(dim3(WPB), st, nullptr, 0, lower, p, split, Tinv,
                      InvDirect{T, ldt, trans, (int)m, dinv});
     return hipGetLastError();
 }
