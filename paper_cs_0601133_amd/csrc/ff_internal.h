@@ -269,9 +269,8 @@ hipError_t launch_trsm_dinv(const uint32_t *T, int64_t ldt, int64_t m, uint32_t 
 hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower, int64_t m,
                             int64_t ldn, uint32_t p, const uint32_t *dinv, uint32_t *Tn,
                             hipStream_t st);
-// B(i, :) <- alpha dinv_i B(i, :) mod p (dinv null: all ones); bt: the m x n
-// matrix B is stored transposed (entry (i, j) at B[j ldb + i]).
-hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int bt, int64_t m, int64_t n, uint32_t p,
+// B(i, :) <- alpha dinv_i B(i, :) mod p (dinv null: all ones).
+hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uint32_t p,
                              uint32_t alpha, const uint32_t *dinv, hipStream_t st);
 // Tinv[g] = inverse of the 64 x 64 diagonal block g of Tn, g < ldn / 64
 // (64 x 64 row-major each); split as for the leaf.
@@ -284,8 +283,8 @@ hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int
                                   int64_t m, uint32_t p, int split, const uint32_t *dinv,
                                   uint32_t *Tinv, hipStream_t st);
 // B(i, :) <- alpha inv(T(i, i)) B(i, :) mod p with the inverses taken in the
-// same launch (unit: alpha only), written to dinv_out unless null; bt as for
-// launch_trsm_scale.  Replaces launch_trsm_dinv + launch_trsm_scale where no
+// same launch (unit: alpha only), written to dinv_out unless null; bt: the
+// m x n matrix B is stored transposed (entry (i, j) at B[j ldb + i]).  Replaces launch_trsm_dinv + launch_trsm_scale where no
 // count of non-invertible diagonal entries is wanted.
 hipError_t launch_trsm_dscale(const uint32_t *T, int64_t ldt, int unit, uint32_t *B,
                               int64_t ldb, int bt, int64_t m, int64_t n, uint32_t p,

@@ -122,29 +122,6 @@ __global__ __launch_bounds__(TT) void k_trsm_scale(uint32_t *B, int64_t ldb, int
     }
 }
 
-// The same for B stored transposed (entry (i, j) at Bt[j ldb + i]): row j of
-// the storage holds column j of B, whose entry i takes the factor of row i.
-__global__ __launch_bounds__(TT) void k_trsm_scale_t(uint32_t *Bt, int64_t ldb, int64_t m,
-                                                     int64_t n, uint32_t p, double pinv,
-                                                     uint32_t alpha, const uint32_t *dinv)
-{
-    const int64_t i0 = (int64_t)blockIdx.x * 4 * TT + threadIdx.x;
-    uint32_t f[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t i = i0 + u * TT;
-        f[u] = i < m ? (dinv ? mulmod(alpha, dinv[i], p, pinv) : alpha) : 0u;
-    }
-    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
-        uint32_t *row = Bt + j * ldb;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t i = i0 + u * TT;
-            if (i < m) row[i] = mulmod(f[u], row[i], p, pinv);
-        }
-    }
-}
-
 // B(i, j) <- alpha dinv_i B(i, j) with dinv_i the inverse of T(i, i) taken
 // here (unit: none), in one pass: every workgroup inverts the diagonal
 // entries of the rows it scales, and one column of workgroups also writes
@@ -622,15 +599,9 @@ hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower
     return hipGetLastError();
 }
 
-hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int bt, int64_t m, int64_t n, uint32_t p,
+hipError_t launch_trsm_scale(uint32_t *B, int64_t ldb, int64_t m, int64_t n, uint32_t p,
                              uint32_t alpha, const uint32_t *dinv, hipStream_t st)
 {
-    if (bt) {
-        const dim3 grid((unsigned)((m + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(n, 4096));
-        hipLaunchKernelGGL(k_trsm_scale_t, grid, dim3(TT), 0, st, B, ldb, m, n, p,
-                           1.0 / (double)p, alpha, dinv);
-        return hipGetLastError();
-    }
     const dim3 grid((unsigned)((n + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(m, 4096));
     hipLaunchKernelGGL(k_trsm_scale, grid, dim3(TT), 0, st, B, ldb, m, n, p, 1.0 / (double)p,
                        alpha, dinv);

@@ -178,8 +178,12 @@ int ftrsm_run(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, 
         FF_HIP_CHECK(launch_trsm_prep(T, ldt, transT == FF_TRANS, lower, m, ldn, p, dv, Tn, st));
         FF_HIP_CHECK(launch_trsm_inv(Tn, ldn, lower, p, split, Tinv, st));
     }
-    if (!fused && (alpha != 1 || !unit))
-        FF_HIP_CHECK(launch_trsm_scale(B, ldb, bt, m, n, p, alpha, dv, st));
+    if (!fused && (alpha != 1 || !unit)) {
+        if (bt) // (validated above; the pass takes the inverses again)
+            FF_HIP_CHECK(launch_trsm_dscale(T, ldt, unit, B, ldb, 1, m, n, p, alpha, nullptr, st));
+        else
+            FF_HIP_CHECK(launch_trsm_scale(B, ldb, m, n, p, alpha, dv, st));
+    }
     Trsm c;
     c.p = p;
     c.lower = lower;
