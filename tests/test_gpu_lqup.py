@@ -218,3 +218,41 @@ def test_inverse_full_size_sampled_rows(n):
     rows = np.random.default_rng(n).choice(n, 6, replace=False)
     XA = oracle.fgemm(p, np.ascontiguousarray(X[rows]), A, np.zeros((6, n), np.uint32))
     assert np.array_equal(XA, np.eye(n, dtype=np.uint32)[rows])
+
+
+def test_concurrent_factorisations_on_two_streams():
+    # two host threads factor different matrices at once, each on a torch
+    # stream of its own: every call borrows its own second stream (the
+    # panels' solves past the window run there) and per-stream workspace,
+    # so the results must be those of the oracle, every repetition
+    import threading
+    import torch
+    p = 8388593
+    shapes = [(256, 300), (320, 320)]          # m <= n: the full-rank fast path
+    mats = [synth.residues(synth.seed_for(170 + i, 1), s, p) for i, s in enumerate(shapes)]
+    want = [oracle.lqup(p, A) for A in mats]
+    errors = []
+
+    def work(i):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for rep in range(4):
+                    dA = torch.from_numpy(mats[i].view(np.int32)).to("cuda", non_blocking=False)
+                    r, piv, perm = ff.lqup(p, dA)
+                    s.synchronize()
+                    F = dA.cpu().numpy().view(np.uint32)
+                    F0, r0, piv0, perm0 = want[i]
+                    if not (r == r0 and np.array_equal(F, F0) and np.array_equal(piv, piv0)
+                            and np.array_equal(perm, perm0)):
+                        errors.append((i, rep))
+        except Exception as e:  # reported below, on the test's thread
+            errors.append((i, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(i,), daemon=True) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads), "a factorisation did not return"
+    assert not errors, errors
