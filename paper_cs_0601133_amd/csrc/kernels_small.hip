@@ -81,6 +81,11 @@ __global__ __launch_bounds__(STH) void k_fgemm_f64_small(F64Small J)
     const int m0 = blockIdx.y * ST, n0 = blockIdx.x * ST;
     const uint32_t half = (J.p - 1) / 2;
     const int nst = (J.k + SKS - 1) / SKS;
+    // thread t finishes entry (t / 16, t % 16) of the block; its entry of C
+    // is requested now (clamped into C, no branch) so that the read is done
+    // by the time the products are
+    const int gr = m0 + (t >> 4), gc = n0 + (t & 15);
+    const uint32_t cin = J.beta ? J.C[(int64_t)min(gr, J.m - 1) * J.ldc + min(gc, J.n - 1)] : 0u;
 
     // two accumulators (even and odd steps) halve the dependent chain; the
     // K-block counts the products of both
@@ -175,18 +180,14 @@ __global__ __launch_bounds__(STH) void k_fgemm_f64_small(F64Small J)
         sR[w][((lane >> 4) + 4 * r) * ST + (lane & 15)] = e0 + e1;
     }
     __syncthreads();
-    // thread t finishes entry (t / 16, t % 16) of the block
-    const int i = t >> 4, j = t & 15;
-    const int gr = m0 + i, gc = n0 + j;
     if (gr < J.m && gc < J.n) {
         double x = 0.0;
 #pragma unroll
         for (int v = 0; v < NW; ++v) x += sR[v][t];
         const uint32_t val = canon_f64(x, J.pd, J.pinv, J.p);
         uint32_t out = mulmod(J.alpha, val, J.p, J.pinv);
-        uint32_t *cp = J.C + (int64_t)gr * J.ldc + gc;
-        if (J.beta) out = addmod(out, mulmod(J.beta, *cp, J.p, J.pinv), J.p);
-        *cp = out;
+        if (J.beta) out = addmod(out, mulmod(J.beta, cin, J.p, J.pinv), J.p);
+        J.C[(int64_t)gr * J.ldc + gc] = out;
     }
 }
 
