@@ -601,7 +601,7 @@ def serving(torch, ff, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_cs_0601133_amd import ffgemm as ff
