@@ -59,28 +59,31 @@ __global__ __launch_bounds__(TT) void k_trsm_dinv(const uint32_t *T, int64_t ldt
 }
 
 // T'(i, j) = dinv_i op(T)(i, j) (dinv null: unit diagonal, all ones) inside
-// the triangle (i, j < m), 1 on the
-// whole diagonal, 0 elsewhere; ldn x ldn row-major, ldn = m rounded up to a
-// multiple of 64, so that every 64-row block is whole and its padding rows
-// and columns are those of the identity.  One workgroup per 64 x 64 tile:
-// tiles outside the triangle are written as zeros without reading T, and
-// op(T) = T^T goes through LDS so that both the reads and the writes run
-// along rows.
+// the triangle (i, j < m), 1 on the whole diagonal, 0 elsewhere; ldn x ldn
+// row-major, ldn = m rounded up to a multiple of 64, so that every 64-row
+// block is whole and its padding rows and columns are those of the
+// identity.  One workgroup per 64 x 64 tile of the triangle (diagonal tiles
+// included); the tiles beyond it are not written, since no kernel reads them
+// (the inverses read diagonal tiles, the leaves and the updates tiles inside
+// the triangle).  op(T) = T^T goes through LDS so that both the reads and
+// the writes run along rows.
 __global__ __launch_bounds__(TT) void k_trsm_prep(const uint32_t *T, int64_t ldt, int trans,
                                                   int lower, int64_t m, int64_t ldn, uint32_t p,
                                                   double pinv, const uint32_t *dinv,
                                                   uint32_t *Tn)
 {
     __shared__ uint32_t tile[64][65];
-    const int64_t nt = ldn / 64;
-    const int64_t ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    // workgroup b takes the b-th tile of the triangle, numbered row by row
+    // in the lower-triangle order (a, c), c <= a, and mirrored for upper
+    const int64_t b = blockIdx.x;
+    int64_t a = (int64_t)((__builtin_sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while (a * (a + 1) / 2 > b) --a;
+    while ((a + 1) * (a + 2) / 2 <= b) ++a;
+    const int64_t cb = b - a * (a + 1) / 2;
+    const int64_t ti = lower ? a : cb, tj = lower ? cb : a;
     const int c = threadIdx.x & 63, r4 = threadIdx.x >> 6;
     const int64_t i0 = 64 * ti, j0 = 64 * tj;
     uint32_t *dst = Tn + i0 * ldn + j0;
-    if (lower ? tj > ti : tj < ti) {
-        for (int r = r4; r < 64; r += 4) dst[(int64_t)r * ldn + c] = 0u;
-        return;
-    }
     // op(T)(i0 + r, j0 + c) into tile[r][c]
     for (int r = r4; r < 64; r += 4) {
         uint32_t v = 0;
@@ -592,7 +595,7 @@ hipError_t launch_trsm_prep(const uint32_t *T, int64_t ldt, int trans, int lower
                             int64_t ldn, uint32_t p, const uint32_t *dinv, uint32_t *Tn,
                             hipStream_t st)
 {
-    const int64_t tiles = (ldn / 64) * (ldn / 64);
+    const int64_t nt = ldn / 64, tiles = nt * (nt + 1) / 2; // the triangle's tiles
     if (tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_trsm_prep, dim3((unsigned)tiles), dim3(TT), 0, st, T, ldt, trans, lower,
                        m, ldn, p, 1.0 / (double)p, dinv, Tn);
