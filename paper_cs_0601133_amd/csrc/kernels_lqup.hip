@@ -6,6 +6,8 @@
 // exchanges the pivots require (k_lqup_swap), the gathering of the pivot rows
 // (k_lqup_gather) and a search for pivots past the panel's window
 // (k_lqup_first_nonzero).
+#include <type_traits>
+
 #include "ff_device.h"
 #include "ff_internal.h"
 
@@ -256,6 +258,220 @@ __global__ __launch_bounds__(PT) void k_lqup_panel(uint32_t *A, int64_t lda, int
     if (tid < PR) out[3 + tid] = s_rowpiv[tid];
 }
 
+// Lane l's value of x, in every lane (l uniform).
+__device__ __forceinline__ double readlane_d(double x, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Polls of a publication flag before a wave gives up (each poll is an LDS
+// round trip; a step's wait is a few hundred cycles).
+constexpr int SPIN_LIMIT = 1 << 20;
+
+__device__ __forceinline__ bool wait_flag(int *f, bool tight)
+{
+    for (int it = 0; it < SPIN_LIMIT; ++it) {
+        if (__builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)))
+            return true;
+        if (!tight) __builtin_amdgcn_s_sleep(1);
+    }
+    return false;
+}
+
+// Panel of the full-rank guess: rows [i0, i0 + nr) taken to pivot in columns
+// k, k + 1, ... in order, with no exchange.  The guess holds unless a pivot
+// value is 0 (or nr > W); then *fail is set and the caller redoes the
+// factorisation on the general path, so this kernel needs no pivot search,
+// column exchange or stop.
+//
+// Elimination is fraction free, as in k_lqup_panel; the synchronisation is
+// not a barrier per row.  Row r is published once, into LDS slot r, by the
+// wave that holds it, right after its update by row r - 1, and a release
+// flag follows.  A wave waits only for the row it needs next and takes its
+// multipliers from its own registers (lane r of each of its rows), so waves
+// run ahead of one another.  The critical path is one row's update per step,
+// plus, every PQ rows, the hand-over to the next wave through LDS.  A
+// wave whose rows are all finished leaves the loop.
+//
+// Below pivot row r, columns c <= r are scaled by the pivot instead of being
+// kept, so the multiplier in column c of row r2 ends up carrying the pivots
+// c .. r2 - 1 of the steps it went through: L = stored S_c / (pi_c S_r2),
+// with S_j = pi_0 ... pi_{j-1}; a U entry is stored / S_r2 as before.
+//
+// Workgroup b also carries the nc columns past the window, 64 of them from
+// column k + W + 64 b, through the same row operations, so that the pivot
+// rows' entries there leave finished (the caller's unit lower triangular
+// solve for them, fused).  Every workgroup factors the window, which they
+// all read, so the last one to finish (ctr[2], left zero) writes it, and
+// sets *fail to 1 for a zero pivot, 2 if a wait gave up.
+template <bool CARRY>
+__global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0,
+                                                        int nr, int64_t k, int W, int64_t nc,
+                                                        uint32_t p, double pinv, int32_t *fail,
+                                                        unsigned *ctr)
+{
+    __shared__ double s_row[PR][PW];                // published rows, window
+    __shared__ double s_rowx[CARRY ? PR : 1][64];   // and carried columns
+    __shared__ int s_flag[PR];
+    __shared__ uint32_t s_inv[PR], s_S[PR + 1], s_invS[PR + 1];
+    __shared__ int s_bad, s_last;
+    const int tid = threadIdx.x, c = tid % 64;
+    const int g = __builtin_amdgcn_readfirstlane(tid / 64);
+    const uint32_t half = (p - 1) / 2;
+    const double pd = (double)p;
+    const int64_t x0 = k + W + 64 * (int64_t)blockIdx.x;
+    const int64_t xleft = nc - 64 * (int64_t)blockIdx.x;
+    const int xw = CARRY ? (int)(xleft < 64 ? xleft : 64) : 0;
+
+    double v[PQ], x[PQ];
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+        const int r = PQ * g + q;
+        uint32_t u = 0, ux = 0;
+        if (r < nr && c < W) u = A[(i0 + r) * lda + k + c];
+        if (CARRY && r < nr && c < xw) ux = A[(i0 + r) * lda + x0 + c];
+        v[q] = (double)center(u, p, half);
+        x[q] = (double)center(ux, p, half);
+    }
+    if (tid < PR) s_flag[tid] = 0;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    if (g == 0) {
+        s_row[0][c] = v[0];
+        if (CARRY) s_rowx[0][c] = x[0];
+        __hip_atomic_store(&s_flag[0], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
+    int gave_up = 0;
+    // step r: the rows after r, by pivot row r (column r)
+    for (int r = 0; r + 1 < nr; ++r) {
+        if (PQ * g + PQ - 1 <= r) break; // this wave's rows are finished
+        const int gn = (r + 1) / PQ, qn = (r + 1) % PQ;
+        double y, yx = 0.0;
+        if (g == gn && qn != 0) {
+            // row r is this wave's row qn - 1
+            y = qn == 1 ? v[0] : qn == 2 ? v[1] : v[2];
+            if (CARRY) yx = qn == 1 ? x[0] : qn == 2 ? x[1] : x[2];
+        } else {
+            if (!gave_up) gave_up = !wait_flag(&s_flag[r], g == gn);
+            y = s_row[r][c];
+            if (CARRY) yx = s_rowx[r][c];
+        }
+        const double pv = readlane_d(y, r);
+        const double ye = c > r && c < W ? y : 0.0;
+        // rows [q0, q1) of this wave: the multipliers first, then each stage
+        // for all rows, so that their chains of dependent operations overlap
+        auto update = [&](auto q0c, auto q1c) {
+            constexpr int q0 = decltype(q0c)::value, q1 = decltype(q1c)::value;
+            double a[PQ], t[PQ], tx[PQ];
+#pragma unroll
+            for (int q = q0; q < q1; ++q) a[q] = readlane_d(v[q], r);
+#pragma unroll
+            for (int q = q0; q < q1; ++q) {
+                t[q] = __builtin_fma(pv, v[q], -a[q] * ye);
+                if (CARRY) tx[q] = __builtin_fma(pv, x[q], -a[q] * yx);
+            }
+#pragma unroll
+            for (int q = q0; q < q1; ++q) {
+                v[q] = reduce_c(t[q], pd, pinv);
+                if (CARRY) x[q] = reduce_c(tx[q], pd, pinv);
+            }
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        using I4 = std::integral_constant<int, 4>;
+        auto publish = [&](double w, double wx) {
+            s_row[r + 1][c] = w;
+            if (CARRY) s_rowx[r + 1][c] = wx;
+        };
+        if (g == gn) {
+            // row r + 1 (this wave's row qn) first, at raised priority: its
+            // entries go out before the rows after it are updated, the flag
+            // after them
+            __builtin_amdgcn_s_setprio(3);
+            switch (qn) {
+            case 0:
+                update(I0{}, I1{}); publish(v[0], x[0]); update(I1{}, I4{});
+                break;
+            case 1:
+                update(I1{}, I2{}); publish(v[1], x[1]); update(I2{}, I4{});
+                break;
+            case 2:
+                update(I2{}, I3{}); publish(v[2], x[2]); update(I3{}, I4{});
+                break;
+            default:
+                update(I3{}, I4{}); publish(v[3], x[3]);
+                break;
+            }
+            __hip_atomic_store(&s_flag[r + 1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            __builtin_amdgcn_s_setprio(0);
+            update(I0{}, I4{});
+        }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    if (gave_up && c == 0) atomicOr(&s_bad, 2);
+    __syncthreads();
+    // pivots pi_j: row j as published (every update applied); inverses, and
+    // the prefix products S_j and 1 / S_j
+    if (tid < 64) {
+        uint32_t pi = 1, iv = 1;
+        if (tid < nr) {
+            pi = canon_f64(s_row[tid][tid], pd, pinv, p);
+            iv = inv_mod(pi, p);
+            if (pi == 0) atomicOr(&s_bad, 1);
+        }
+        s_inv[tid] = iv;
+        uint32_t sp = pi, si = iv; // inclusive products over lanes <= tid
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t up = __shfl_up(sp, d, 64), ui = __shfl_up(si, d, 64);
+            if (tid >= d) {
+                sp = mulmod(sp, up, p, pinv);
+                si = mulmod(si, ui, p, pinv);
+            }
+        }
+        s_S[tid + 1] = sp;
+        s_invS[tid + 1] = si;
+        if (tid == 0) {
+            s_S[0] = 1u;
+            s_invS[0] = 1u;
+            s_last = gridDim.x == 1 || atomicAdd(&ctr[2], 1u) == gridDim.x - 1;
+        }
+    }
+    __syncthreads();
+    if (CARRY) {
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int r = PQ * g + q;
+            if (r < nr && c < xw)
+                A[(i0 + r) * lda + x0 + c] =
+                    mulmod(canon_f64(x[q], pd, pinv, p), s_invS[r], p, pinv);
+        }
+    }
+    if (!s_last) return;
+    if (c < W) {
+        const uint32_t colf = c < nr ? mulmod(s_S[c], s_inv[c], p, pinv) : 0u;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int r = PQ * g + q;
+            if (r >= nr) continue;
+            const uint32_t f = c < r ? mulmod(colf, s_invS[r], p, pinv) : s_invS[r];
+            A[(i0 + r) * lda + k + c] = mulmod(canon_f64(v[q], pd, pinv, p), f, p, pinv);
+        }
+    }
+    if (tid == 0) {
+        if (s_bad) *fail = s_bad;
+        if (gridDim.x > 1) atomicExch(&ctr[2], 0u);
+    }
+}
+
 // Column exchanges (c1, c2), in order, applied to every row outside
 // [skip_lo, skip_hi); one thread per row.
 __global__ __launch_bounds__(256) void k_lqup_swap(uint32_t *A, int64_t lda, int64_t m,
@@ -326,6 +542,30 @@ hipError_t launch_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr, int64
     else
         hipLaunchKernelGGL(k_lqup_panel<false>, dim3(1), dim3(PT), 0, st, A, lda, i0, nr, k, W,
                            whole, p, 1.0 / (double)p, out, fail);
+    return hipGetLastError();
+}
+
+bool lqup_panel_fast_ok(uint32_t p)
+{
+    const double h = (double)(p / 2) + 2.0;
+    return 2.0 * h * h <= 9007199254740992.0;
+}
+
+hipError_t launch_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
+                                  int64_t nc, uint32_t p, int32_t *fail, unsigned *ctr,
+                                  hipStream_t st)
+{
+    if (nr < 1 || nr > PR || W < 1 || W > PW || nc < 0 || !fail || !ctr ||
+        !lqup_panel_fast_ok(p))
+        return hipErrorInvalidValue;
+    const int64_t nb = nc > 0 ? (nc + 63) / 64 : 1;
+    if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    if (nc > 0)
+        hipLaunchKernelGGL(k_lqup_panel_fast<true>, dim3((unsigned)nb), dim3(PT), 0, st, A, lda,
+                           i0, nr, k, W, nc, p, 1.0 / (double)p, fail, ctr);
+    else
+        hipLaunchKernelGGL(k_lqup_panel_fast<false>, dim3(1), dim3(PT), 0, st, A, lda, i0, nr, k,
+                           W, nc, p, 1.0 / (double)p, fail, ctr);
     return hipGetLastError();
 }
 

@@ -29,7 +29,11 @@
 // exchange), which fixes every size in advance: nothing is read back per
 // panel, the pivot rows of a half are its rows in place (no gather), and
 // each panel kernel records in a device flag whether the guess held for it.
-// Each panel's solve for its pivot rows past the window runs on a second
+// While centered products are exact in binary64 (p below about 2^26.5) a
+// panel is one launch of k_lqup_panel_fast, which carries the pivot rows'
+// entries past the window through its own row operations (the solve for
+// them, fused; one workgroup per 64 of those columns).  For larger p each
+// panel's solve for its pivot rows past the window is an ftrsm on a second
 // stream, beside the right-hand solve that follows it (see Aux).
 // The flag is read once at the end; if any panel saw otherwise, A is
 // restored from a copy taken at the start and the factorisation runs again
@@ -48,7 +52,8 @@ namespace ff {
 namespace {
 
 // A second stream and two events, borrowed per factorisation from a pool
-// per device: on the fast path each panel's solve for its pivot rows past
+// per device: on the fast path with the general panel kernel (large p),
+// each panel's solve for its pivot rows past
 // the window runs there, beside the next right-hand solve (which does not
 // read those entries); the main stream waits for it before the update that
 // does.  Both are latency-bound launches of a few workgroups.
@@ -107,7 +112,9 @@ struct Lqup {
     std::vector<char> dep;    // dependent rows
     std::vector<int64_t> colperm;
     bool spec = false;      // full-rank guess in force (see above)
+    bool fused = false;     // its panels by k_lqup_panel_fast (p small enough)
     int32_t *d_fail = nullptr; // set by a panel that contradicts the guess
+    unsigned *ctr = nullptr;   // the stream's counter block (fused panels)
     Aux aux;                // second stream (fast path), if one was had
     bool have_aux = false;
     bool y_pending = false; // a panel's solve past its window still runs on aux.st
@@ -154,9 +161,15 @@ int panel_guess(Lqup &c, int64_t a, int64_t b, int64_t *found)
     const int nr = (int)(b - a);
     const int W = (int)std::min<int64_t>(LQUP_WINDOW, c.n - c.k);
     const int whole = c.k + W == c.n;
-    FF_HIP_CHECK(launch_lqup_panel(c.A, c.lda, a, nr, c.k, W, whole, c.p, c.d_out, c.st,
-                                   c.d_fail));
-    if (!whole && nr <= W) {
+    if (c.fused) {
+        // one launch: the panel and its rows past the window
+        FF_HIP_CHECK(launch_lqup_panel_fast(c.A, c.lda, a, nr, c.k, W, whole ? 0 : c.n - c.k - W,
+                                            c.p, c.d_fail, c.ctr, c.st));
+    } else {
+        FF_HIP_CHECK(launch_lqup_panel(c.A, c.lda, a, nr, c.k, W, whole, c.p, c.d_out, c.st,
+                                       c.d_fail));
+    }
+    if (!c.fused && !whole && nr <= W) {
         const int64_t nc = c.n - c.k - W;
         uint32_t *T = c.A + a * c.lda + c.k;
         ff_opts o = c.o;
@@ -383,7 +396,12 @@ int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
                                       (size_t)m, hipMemcpyDeviceToDevice, c.st));
         FF_HIP_CHECK(launch_scale((uint32_t *)c.d_fail, 1, 1, 1, 2u, 0u, c.st));
         c.spec = true;
-        c.have_aux = aux_acquire(&c.aux); // else everything stays on c.st
+        c.fused = lqup_panel_fast_ok(p);
+        if (c.fused) {
+            if ((rc = counter_buffer(c.st, &c.ctr))) return rc;
+        } else {
+            c.have_aux = aux_acquire(&c.aux); // else everything stays on c.st
+        }
         rc = rec(c, 0, m, &found);
         if (rc) return rc;
         if ((rc = wait_y(c))) return rc;
@@ -391,11 +409,13 @@ int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
         FF_HIP_CHECK(hipMemcpyAsync(&failed, c.d_fail, sizeof(failed), hipMemcpyDeviceToHost,
                                     c.st));
         FF_HIP_CHECK(hipStreamSynchronize(c.st));
+        if (failed & 2) return fail(FF_EHIP, "internal error: an LQUP panel's wait gave up");
         guessed = failed == 0;
         if (!guessed) {
             FF_HIP_CHECK(hipMemcpy2DAsync(A, (size_t)lda * 4, bk, (size_t)n * 4, (size_t)n * 4,
                                           (size_t)m, hipMemcpyDeviceToDevice, c.st));
             c.spec = false;
+            c.fused = false;
             c.k = 0;
             c.piv.clear();
             c.dep.assign(m, 0);
