@@ -312,12 +312,15 @@ hipError_t launch_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr, int64
 // ... in order, or *fail becomes nonzero (1: a zero pivot or nr > W; 2: the
 // kernel's internal wait gave up, an error).  The nc columns past the window
 // [k, k + W) leave as the pivot rows' U entries (the unit lower triangular
-// solve fused).  ctr: the stream's zeroed counter block (word 2, left zero).
-// Only for p with lqup_panel_fast_ok(p) (centered products exact in binary64).
+// solve fused).  m2 > 0 (needs nr == W): rows [g0, g0 + m2) of the window
+// are overwritten by G with G T = X, T the panel's U in the window (the
+// right-hand solve for the rows below, fused).  ctr: the stream's zeroed
+// counter block (word 2, left zero).  Only for p with lqup_panel_fast_ok(p)
+// (centered products exact in binary64).
 bool lqup_panel_fast_ok(uint32_t p);
 hipError_t launch_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
-                                  int64_t nc, uint32_t p, int32_t *fail, unsigned *ctr,
-                                  hipStream_t st);
+                                  int64_t nc, int64_t g0, int m2, uint32_t p, int32_t *fail,
+                                  unsigned *ctr, hipStream_t st);
 // Column exchanges pairs[2j] <-> pairs[2j + 1] in order, rows outside
 // [skip_lo, skip_hi).
 hipError_t launch_lqup_swap(uint32_t *A, int64_t lda, int64_t m, int64_t skip_lo, int64_t skip_hi,

@@ -305,14 +305,25 @@ __device__ __forceinline__ bool wait_flag(int *f, bool tight)
 // Workgroup b also carries the nc columns past the window, 64 of them from
 // column k + W + 64 b, through the same row operations, so that the pivot
 // rows' entries there leave finished (the caller's unit lower triangular
-// solve for them, fused).  Every workgroup factors the window, which they
-// all read, so the last one to finish (ctr[2], left zero) writes it, and
-// sets *fail to 1 for a zero pivot, 2 if a wait gave up.
-template <bool CARRY>
+// solve for them, fused).
+//
+// With m2 > 0 (and nr == W) the last ceil(m2 / 16) workgroups eliminate the
+// m2 rows from g0 on over the window by all nr pivot rows, as rows below
+// them, 16 per workgroup, four in each of the last four waves (those stay to
+// the end anyway: the workgroup's work is then that of a carrying one).
+// The multipliers are G with G T = X, T the
+// panel's U in the window and X those rows' window entries (the caller's
+// right-hand triangular solve for the rows below the panel, fused), stored
+// over X.
+//
+// Every workgroup factors the window, which they all read, so the last one
+// to finish (ctr[2], left zero) writes it, and sets *fail to 1 for a zero
+// pivot, 2 if a wait gave up.
+template <bool CARRY, bool FOLD>
 __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0,
                                                         int nr, int64_t k, int W, int64_t nc,
-                                                        uint32_t p, double pinv, int32_t *fail,
-                                                        unsigned *ctr)
+                                                        int64_t g0, int m2, uint32_t p,
+                                                        double pinv, int32_t *fail, unsigned *ctr)
 {
     __shared__ double s_row[PR][PW];                // published rows, window
     __shared__ double s_rowx[CARRY ? PR : 1][64];   // and carried columns
@@ -323,9 +334,17 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
     const int g = __builtin_amdgcn_readfirstlane(tid / 64);
     const uint32_t half = (p - 1) / 2;
     const double pd = (double)p;
+    // gwg: a workgroup of the rows below, whose last four waves hold four of
+    // them each (below; x[q] the window entries of row gb + q of them); xc: x
+    // holds carried columns (all uniform)
+    const int ng = (m2 + 15) / 16;
+    const bool gwg = FOLD && (int)blockIdx.x >= (int)gridDim.x - ng;
+    const bool xc = CARRY && !gwg;
+    const bool below = gwg && g >= PG - 4;
+    const int gb = 16 * ((int)blockIdx.x - ((int)gridDim.x - ng)) + PQ * (g - (PG - 4));
     const int64_t x0 = k + W + 64 * (int64_t)blockIdx.x;
     const int64_t xleft = nc - 64 * (int64_t)blockIdx.x;
-    const int xw = CARRY ? (int)(xleft < 64 ? xleft : 64) : 0;
+    const int xw = xc ? (int)(xleft < 64 ? xleft : 64) : 0;
 
     double v[PQ], x[PQ];
 #pragma unroll
@@ -333,7 +352,8 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
         const int r = PQ * g + q;
         uint32_t u = 0, ux = 0;
         if (r < nr && c < W) u = A[(i0 + r) * lda + k + c];
-        if (CARRY && r < nr && c < xw) ux = A[(i0 + r) * lda + x0 + c];
+        if (xc && r < nr && c < xw) ux = A[(i0 + r) * lda + x0 + c];
+        if (below && gb + q < m2 && c < W) ux = A[(g0 + gb + q) * lda + k + c];
         v[q] = (double)center(u, p, half);
         x[q] = (double)center(ux, p, half);
     }
@@ -342,77 +362,100 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
     __syncthreads();
     if (g == 0) {
         s_row[0][c] = v[0];
-        if (CARRY) s_rowx[0][c] = x[0];
+        if (xc) s_rowx[0][c] = x[0];
         __hip_atomic_store(&s_flag[0], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
     int gave_up = 0;
-    // step r: the rows after r, by pivot row r (column r)
-    for (int r = 0; r + 1 < nr; ++r) {
-        if (PQ * g + PQ - 1 <= r) break; // this wave's rows are finished
+    // step r: the rows after r, by pivot row r (column r); the rows below
+    // the panel take every pivot row, the panel's own rows all but the last
+    const int steps = gwg ? nr : nr - 1;
+    for (int r = 0; r < steps; ++r) {
+        const bool done = PQ * g + PQ - 1 <= r; // this wave's panel rows are finished
+        if (done && !below) break;
         const int gn = (r + 1) / PQ, qn = (r + 1) % PQ;
         double y, yx = 0.0;
         if (g == gn && qn != 0) {
             // row r is this wave's row qn - 1
             y = qn == 1 ? v[0] : qn == 2 ? v[1] : v[2];
-            if (CARRY) yx = qn == 1 ? x[0] : qn == 2 ? x[1] : x[2];
+            if (xc) yx = qn == 1 ? x[0] : qn == 2 ? x[1] : x[2];
         } else {
             if (!gave_up) gave_up = !wait_flag(&s_flag[r], g == gn);
             y = s_row[r][c];
-            if (CARRY) yx = s_rowx[r][c];
+            if (xc) yx = s_rowx[r][c];
         }
         const double pv = readlane_d(y, r);
         const double ye = c > r && c < W ? y : 0.0;
-        // rows [q0, q1) of this wave: the multipliers first, then each stage
-        // for all rows, so that their chains of dependent operations overlap
-        auto update = [&](auto q0c, auto q1c) {
-            constexpr int q0 = decltype(q0c)::value, q1 = decltype(q1c)::value;
-            double a[PQ], t[PQ], tx[PQ];
-#pragma unroll
-            for (int q = q0; q < q1; ++q) a[q] = readlane_d(v[q], r);
-#pragma unroll
-            for (int q = q0; q < q1; ++q) {
-                t[q] = __builtin_fma(pv, v[q], -a[q] * ye);
-                if (CARRY) tx[q] = __builtin_fma(pv, x[q], -a[q] * yx);
-            }
-#pragma unroll
-            for (int q = q0; q < q1; ++q) {
-                v[q] = reduce_c(t[q], pd, pinv);
-                if (CARRY) x[q] = reduce_c(tx[q], pd, pinv);
-            }
-        };
         using I0 = std::integral_constant<int, 0>;
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
         using I3 = std::integral_constant<int, 3>;
         using I4 = std::integral_constant<int, 4>;
-        auto publish = [&](double w, double wx) {
-            s_row[r + 1][c] = w;
-            if (CARRY) s_rowx[r + 1][c] = wx;
-        };
-        if (g == gn) {
-            // row r + 1 (this wave's row qn) first, at raised priority: its
-            // entries go out before the rows after it are updated, the flag
-            // after them
-            __builtin_amdgcn_s_setprio(3);
-            switch (qn) {
-            case 0:
-                update(I0{}, I1{}); publish(v[0], x[0]); update(I1{}, I4{});
-                break;
-            case 1:
-                update(I1{}, I2{}); publish(v[1], x[1]); update(I2{}, I4{});
-                break;
-            case 2:
-                update(I2{}, I3{}); publish(v[2], x[2]); update(I3{}, I4{});
-                break;
-            default:
-                update(I3{}, I4{}); publish(v[3], x[3]);
-                break;
+        // the panel's rows of this wave after r; WX: with their carried
+        // columns (x), else x is left alone
+        auto own_rows = [&](auto wxc) {
+            constexpr bool WX = decltype(wxc)::value;
+            // rows [q0, q1): the multipliers first, then each stage for all
+            // rows, so that their chains of dependent operations overlap
+            auto update = [&](auto q0c, auto q1c) {
+                constexpr int q0 = decltype(q0c)::value, q1 = decltype(q1c)::value;
+                double a[PQ], t[PQ], tx[PQ];
+#pragma unroll
+                for (int q = q0; q < q1; ++q) a[q] = readlane_d(v[q], r);
+#pragma unroll
+                for (int q = q0; q < q1; ++q) {
+                    t[q] = __builtin_fma(pv, v[q], -a[q] * ye);
+                    if (WX) tx[q] = __builtin_fma(pv, x[q], -a[q] * yx);
+                }
+#pragma unroll
+                for (int q = q0; q < q1; ++q) {
+                    v[q] = reduce_c(t[q], pd, pinv);
+                    if (WX) x[q] = reduce_c(tx[q], pd, pinv);
+                }
+            };
+            auto publish = [&](double w, double wx) {
+                s_row[r + 1][c] = w;
+                if (WX) s_rowx[r + 1][c] = wx;
+            };
+            if (g == gn) {
+                // row r + 1 (this wave's row qn) first, at raised priority:
+                // its entries go out before the rows after it are updated,
+                // the flag after them
+                __builtin_amdgcn_s_setprio(3);
+                switch (qn) {
+                case 0:
+                    update(I0{}, I1{}); publish(v[0], x[0]); update(I1{}, I4{});
+                    break;
+                case 1:
+                    update(I1{}, I2{}); publish(v[1], x[1]); update(I2{}, I4{});
+                    break;
+                case 2:
+                    update(I2{}, I3{}); publish(v[2], x[2]); update(I3{}, I4{});
+                    break;
+                default:
+                    update(I3{}, I4{}); publish(v[3], x[3]);
+                    break;
+                }
+                __hip_atomic_store(&s_flag[r + 1], 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                __builtin_amdgcn_s_setprio(0);
+                update(I0{}, I4{});
             }
-            __hip_atomic_store(&s_flag[r + 1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-            __builtin_amdgcn_s_setprio(0);
-            update(I0{}, I4{});
+        };
+        if (!done) {
+            if (xc) own_rows(std::integral_constant<bool, CARRY>{});
+            else own_rows(std::false_type{});
+        }
+        if (FOLD && below) {
+            // the wave's rows below the panel, by their own multipliers
+            double a[PQ], t[PQ];
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) a[q] = readlane_d(x[q], r);
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) t[q] = __builtin_fma(pv, x[q], -a[q] * ye);
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) x[q] = reduce_c(t[q], pd, pinv);
         }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -446,7 +489,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
         }
     }
     __syncthreads();
-    if (CARRY) {
+    if (xc) {
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
             const int r = PQ * g + q;
@@ -454,6 +497,15 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
                 A[(i0 + r) * lda + x0 + c] =
                     mulmod(canon_f64(x[q], pd, pinv, p), s_invS[r], p, pinv);
         }
+    }
+    if (below && c < W) {
+        // G = stored S_c / (pi_c S_nr): every pivot row went through it
+        const uint32_t f = mulmod(mulmod(s_S[c], s_inv[c], p, pinv), s_invS[nr], p, pinv);
+#pragma unroll
+        for (int q = 0; q < PQ; ++q)
+            if (gb + q < m2)
+                A[(g0 + gb + q) * lda + k + c] =
+                    mulmod(canon_f64(x[q], pd, pinv, p), f, p, pinv);
     }
     if (!s_last) return;
     if (c < W) {
@@ -552,20 +604,24 @@ bool lqup_panel_fast_ok(uint32_t p)
 }
 
 hipError_t launch_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
-                                  int64_t nc, uint32_t p, int32_t *fail, unsigned *ctr,
-                                  hipStream_t st)
+                                  int64_t nc, int64_t g0, int m2, uint32_t p, int32_t *fail,
+                                  unsigned *ctr, hipStream_t st)
 {
-    if (nr < 1 || nr > PR || W < 1 || W > PW || nc < 0 || !fail || !ctr ||
-        !lqup_panel_fast_ok(p))
+    if (nr < 1 || nr > PR || W < 1 || W > PW || nc < 0 || m2 < 0 || m2 > PR ||
+        (m2 > 0 && nr != W) || !fail || !ctr || !lqup_panel_fast_ok(p))
         return hipErrorInvalidValue;
-    const int64_t nb = nc > 0 ? (nc + 63) / 64 : 1;
+    // carried-column workgroups, then those of the rows below
+    const int64_t nb = (nc + 63) / 64 + (m2 + 15) / 16;
     if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
-    if (nc > 0)
-        hipLaunchKernelGGL(k_lqup_panel_fast<true>, dim3((unsigned)nb), dim3(PT), 0, st, A, lda,
-                           i0, nr, k, W, nc, p, 1.0 / (double)p, fail, ctr);
+    if (m2 > 0)
+        hipLaunchKernelGGL((k_lqup_panel_fast<true, true>), dim3((unsigned)nb), dim3(PT), 0, st, A,
+                           lda, i0, nr, k, W, nc, g0, m2, p, 1.0 / (double)p, fail, ctr);
+    else if (nb > 0)
+        hipLaunchKernelGGL((k_lqup_panel_fast<true, false>), dim3((unsigned)nb), dim3(PT), 0, st,
+                           A, lda, i0, nr, k, W, nc, g0, 0, p, 1.0 / (double)p, fail, ctr);
     else
-        hipLaunchKernelGGL(k_lqup_panel_fast<false>, dim3(1), dim3(PT), 0, st, A, lda, i0, nr, k,
-                           W, nc, p, 1.0 / (double)p, fail, ctr);
+        hipLaunchKernelGGL((k_lqup_panel_fast<false, false>), dim3(1), dim3(PT), 0, st, A, lda, i0,
+                           nr, k, W, nc, g0, 0, p, 1.0 / (double)p, fail, ctr);
     return hipGetLastError();
 }
 

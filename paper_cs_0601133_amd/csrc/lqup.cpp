@@ -113,6 +113,8 @@ struct Lqup {
     std::vector<int64_t> colperm;
     bool spec = false;      // full-rank guess in force (see above)
     bool fused = false;     // its panels by k_lqup_panel_fast (p small enough)
+    int64_t below = 0;      // rows after the next panel whose solve it may fold in
+    bool folded = false;    // the last panel solved G T = X for those rows
     int32_t *d_fail = nullptr; // set by a panel that contradicts the guess
     unsigned *ctr = nullptr;   // the stream's counter block (fused panels)
     Aux aux;                // second stream (fast path), if one was had
@@ -162,9 +164,13 @@ int panel_guess(Lqup &c, int64_t a, int64_t b, int64_t *found)
     const int W = (int)std::min<int64_t>(LQUP_WINDOW, c.n - c.k);
     const int whole = c.k + W == c.n;
     if (c.fused) {
-        // one launch: the panel and its rows past the window
+        // one launch: the panel, its rows past the window and, when the
+        // caller asks and the panel is 64 rows over a 64-column window, the
+        // right-hand solve of the rows below it
+        const int m2 = nr == W && W == LQUP_PANEL ? (int)c.below : 0;
         FF_HIP_CHECK(launch_lqup_panel_fast(c.A, c.lda, a, nr, c.k, W, whole ? 0 : c.n - c.k - W,
-                                            c.p, c.d_fail, c.ctr, c.st));
+                                            b, m2, c.p, c.d_fail, c.ctr, c.st));
+        c.folded = m2 > 0;
     } else {
         FF_HIP_CHECK(launch_lqup_panel(c.A, c.lda, a, nr, c.k, W, whole, c.p, c.d_out, c.st,
                                        c.d_fail));
@@ -272,7 +278,14 @@ int rec(Lqup &c, int64_t a, int64_t b, int64_t *found)
     const int64_t mid = a + round_up((b - a) / 2, LQUP_PANEL);
     const int64_t k0 = c.k;
     int64_t r1 = 0, r2 = 0;
+    // a top half of one panel on the fused fast path solves G T = X for the
+    // bottom half itself (at most 64 rows)
+    c.below = c.spec && c.fused && mid - a == LQUP_PANEL ? b - mid : 0;
+    c.folded = false;
     int rc = rec(c, a, mid, &r1);
+    c.below = 0;
+    const bool folded = c.folded;
+    c.folded = false;
     if (rc) return rc;
     const int64_t m2 = b - mid, nc = c.n - k0;
     if (r1 > 0 && m2 > 0) {
@@ -291,8 +304,11 @@ int rec(Lqup &c, int64_t a, int64_t b, int64_t *found)
         // G T = X  <=>  T^T G^T = X^T, solved in place on X read as the
         // transposed storage of G^T
         uint32_t *X = c.A + mid * c.lda + k0;
-        rc = ftrsm_run(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r1, m2, 1, U, ldu, X, c.lda, 1, &c.o);
-        if (rc) return rc;
+        if (!folded) {
+            rc = ftrsm_run(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r1, m2, 1, U, ldu, X, c.lda, 1,
+                           &c.o);
+            if (rc) return rc;
+        }
         // Y's last columns may still be in the making on the second stream
         if ((rc = wait_y(c))) return rc;
         if (nc > r1) {
