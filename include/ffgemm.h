@@ -257,10 +257,11 @@ int ff_ftrsm_ex(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n
  * row recursion's solves and updates are ff_ftrsm and ff_fgemm calls that
  * follow opts->path.  When m <= n the work first runs on the guess that A
  * has full rank (m pivots in their own columns), which fixes every size in
- * advance; part of it then runs on a second stream the library owns
- * (ordered by events after the work already on opts->stream; all of it has
- * finished when the call returns), and if the guess fails A is restored
- * from a copy and factored again with the pivot search.  A nonzero pivot is
+ * advance.  For p above about 2^26.5 part of that work runs on a second
+ * stream the library owns (ordered by events after the work already on
+ * opts->stream; all of it has finished when the call returns); below, the
+ * panel kernels take that part into their own launches.  If the guess
+ * fails A is restored from a copy and factored again with the pivot search.  A nonzero pivot is
  * assumed invertible (p prime); validate checks the entries of A first.
  * Workspace: about 4 min(m, n) n bytes and, when m <= n, a copy of A
  * (4 m n bytes) per stream, besides those of fgemm and ftrsm. */
