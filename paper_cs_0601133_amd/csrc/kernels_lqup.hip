@@ -607,7 +607,7 @@ hipError_t launch_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0, int nr, 
                                   int64_t nc, int64_t g0, int m2, uint32_t p, int32_t *fail,
                                   unsigned *ctr, hipStream_t st)
 {
-    if (nr < 1 || nr > PR || W < 1 || W > PW || nc < 0 || m2 < 0 || m2 > PR ||
+    if (nr < 1 || nr > PR || W < 1 || W > PW || nc < 0 || m2 < 0 || m2 > (1 << 20) ||
         (m2 > 0 && nr != W) || !fail || !ctr || !lqup_panel_fast_ok(p))
         return hipErrorInvalidValue;
     // carried-column workgroups, then those of the rows below

@@ -40,6 +40,7 @@
 // with the read-backs above.  Either way the result is the same unique
 // factorisation.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -117,6 +118,7 @@ struct Lqup {
     bool folded = false;    // the last panel solved G T = X for those rows
     int32_t *d_fail = nullptr; // set by a panel that contradicts the guess
     unsigned *ctr = nullptr;   // the stream's counter block (fused panels)
+    int64_t cus = 256;         // compute units of the device
     Aux aux;                // second stream (fast path), if one was had
     bool have_aux = false;
     bool y_pending = false; // a panel's solve past its window still runs on aux.st
@@ -272,9 +274,66 @@ int panel(Lqup &c, int64_t a, int64_t b, int64_t *found)
     return FF_OK;
 }
 
+// Whether the fused fast path factors a node of s rows panel by panel
+// (below): the largest nodes whose first panel launch (one workgroup per 64
+// columns past its window, one per 16 rows below it) fits in one round of
+// the device's CUs; past that the launch takes two rounds (n = 4096, ms per
+// factorisation by node size: 128: 5.6, 512: 4.95, 2048: 4.58, 4096: 5.0).
+// FF_LQUP_BLOCK (a multiple of 64 from 64 to 65536) sets the size instead.
+bool blocked_node(const Lqup &c, int64_t s)
+{
+    const char *e = std::getenv("FF_LQUP_BLOCK");
+    if (e && *e) {
+        const int v = std::atoi(e);
+        if (v >= LQUP_PANEL && v <= 65536 && v % LQUP_PANEL == 0) return s <= v;
+    }
+    const int64_t wgs = (c.n - c.k - LQUP_PANEL + 63) / 64 + (s - LQUP_PANEL + 15) / 16;
+    return wgs <= c.cus;
+}
+
+// Fused fast path, rows [a, b) (a node that blocked_node accepts): the panels from
+// left to right, each launch also solving G T = X for every row of the node
+// below the panel (G over X, in the panel's pivot columns), then one fgemm
+// for those rows past the panel's pivot columns, Z <- Z - G Y.  The same
+// products as the recursion's right-hand solves and updates, without the
+// solves.
+int blocked(Lqup &c, int64_t a, int64_t b, int64_t *found)
+{
+    int64_t total = 0;
+    for (int64_t i = a; i < b; i += LQUP_PANEL) {
+        const int64_t e = std::min(i + LQUP_PANEL, b), k0 = c.k, m2 = b - e;
+        int64_t r = 0;
+        c.below = m2;
+        c.folded = false;
+        int rc = panel(c, i, e, &r);
+        c.below = 0;
+        const bool folded = c.folded;
+        c.folded = false;
+        if (rc) return rc;
+        total += r;
+        const int64_t nc = c.n - k0;
+        if (r > 0 && m2 > 0) {
+            const uint32_t *U = c.A + i * c.lda + k0; // the panel's U rows (in place)
+            uint32_t *X = c.A + e * c.lda + k0;
+            if (!folded) {
+                rc = ftrsm_run(c.p, FF_UPPER, FF_TRANS, FF_NONUNIT, r, m2, 1, U, c.lda, X, c.lda,
+                               1, &c.o);
+                if (rc) return rc;
+            }
+            if (nc > r) {
+                rc = fgemm_sub(c, m2, nc - r, r, X, c.lda, U + r, c.lda, X + r, c.lda);
+                if (rc) return rc;
+            }
+        }
+    }
+    *found = total;
+    return FF_OK;
+}
+
 int rec(Lqup &c, int64_t a, int64_t b, int64_t *found)
 {
     if (b - a <= LQUP_PANEL) return panel(c, a, b, found);
+    if (c.spec && c.fused && blocked_node(c, b - a)) return blocked(c, a, b, found);
     const int64_t mid = a + round_up((b - a) / 2, LQUP_PANEL);
     const int64_t k0 = c.k;
     int64_t r1 = 0, r2 = 0;
@@ -415,6 +474,10 @@ int ff_flqup(uint32_t p, int64_t m, int64_t n, uint32_t *A, int64_t lda, int64_t
         c.fused = lqup_panel_fast_ok(p);
         if (c.fused) {
             if ((rc = counter_buffer(c.st, &c.ctr))) return rc;
+            int dev = 0, cus = 0;
+            FF_HIP_CHECK(hipGetDevice(&dev));
+            FF_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            if (cus > 0) c.cus = cus;
         } else {
             c.have_aux = aux_acquire(&c.aux); // else everything stays on c.st
         }

@@ -256,3 +256,19 @@ def test_concurrent_factorisations_on_two_streams():
         t.join(timeout=120)
     assert not any(t.is_alive() for t in threads), "a factorisation did not return"
     assert not errors, errors
+
+
+@pytest.mark.parametrize("block", ["64", "128", "576", "4096"])
+def test_fast_path_node_sizes(block, monkeypatch):
+    # The full-rank fast path factors nodes of up to FF_LQUP_BLOCK rows panel
+    # by panel, each panel launch also solving G T = X for the node's rows
+    # below it (64: never, so the recursion's own solves run; 4096: every
+    # row below each panel, more workgroups than one round of CUs for the
+    # first panels).  Full rank and rank-deficient inputs (the guess fails
+    # and the general path runs), square and wide, ragged last panels.
+    monkeypatch.setenv("FF_LQUP_BLOCK", block)
+    for si, (p, m, n) in enumerate([(8388593, 1000, 1000), (65521, 700, 1090),
+                                     (7, 250, 260)]):
+        A = synth.residues(synth.seed_for(190 + si, 1), (m, n), p)
+        assert_same(p, A)
+    assert_same(65521, known_rank(65521, 600, 640, 590, 191))
