@@ -32,9 +32,11 @@
 // While centered products are exact in binary64 (p below about 2^26.5) a
 // panel is one launch of k_lqup_panel_fast, which carries the pivot rows'
 // entries past the window through its own row operations (the solve for
-// them, fused; one workgroup per 64 of those columns).  For larger p each
-// panel's solve for its pivot rows past the window is an ftrsm on a second
-// stream, beside the right-hand solve that follows it (see Aux).
+// them, fused; one workgroup per 64 of those columns), and nodes small
+// enough (blocked_node) are factored panel by panel, each panel launch also
+// solving G T = X for the node's rows below it.  For larger p each panel's
+// solve for its pivot rows past the window is an ftrsm on a second stream,
+// beside the right-hand solve that follows it (see Aux).
 // The flag is read once at the end; if any panel saw otherwise, A is
 // restored from a copy taken at the start and the factorisation runs again
 // with the read-backs above.  Either way the result is the same unique
