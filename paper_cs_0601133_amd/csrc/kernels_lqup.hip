@@ -485,8 +485,10 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
         if (tid == 0) {
             s_S[0] = 1u;
             s_invS[0] = 1u;
-            s_last = gridDim.x == 1 || atomicAdd(&ctr[2], 1u) == gridDim.x - 1;
         }
+    } else if (tid == 64) {
+        // (a second wave: the counter's round trip beside the inverses)
+        s_last = gridDim.x == 1 || atomicAdd(&ctr[2], 1u) == gridDim.x - 1;
     }
     __syncthreads();
     if (xc) {
