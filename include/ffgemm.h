@@ -81,6 +81,9 @@ enum { FF_PATH_AUTO = 0, FF_PATH_FP64 = 1, FF_PATH_INT8 = 2 };
  *                   by size)
  *   FF_I8_TILE, FF_F64_TILE   force an INT8 / FP64 tile configuration id
  *   FF_TRSM_LEAF    rows per ftrsm leaf launch (64..512, a multiple of 64)
+ *   FF_LQUP_BLOCK   rows of the recursion nodes that ff_flqup's full-rank
+ *                   path factors panel by panel (a multiple of 64; default:
+ *                   the largest whose first panel launch fits the CUs)
  *   FF_TUNE_CACHE   autotuner cache file (see ff_autotune)
  * Every setting gives the same results; only speed changes. */
 
