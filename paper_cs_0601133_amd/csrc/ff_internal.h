@@ -283,12 +283,14 @@ hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int
                                   int64_t m, uint32_t p, int split, const uint32_t *dinv,
                                   uint32_t *Tinv, hipStream_t st);
 // B(i, :) <- alpha inv(T(i, i)) B(i, :) mod p with the inverses taken in the
-// same launch (unit: alpha only), written to dinv_out unless null; bt: the
+// same launch (unit: alpha only), written to dinv_out unless null, or read
+// from dinv_in when it is given (then more workgroups); bt: the
 // m x n matrix B is stored transposed (entry (i, j) at B[j ldb + i]).  Replaces launch_trsm_dinv + launch_trsm_scale where no
 // count of non-invertible diagonal entries is wanted.
 hipError_t launch_trsm_dscale(const uint32_t *T, int64_t ldt, int unit, uint32_t *B,
                               int64_t ldb, int bt, int64_t m, int64_t n, uint32_t p,
-                              uint32_t alpha, uint32_t *dinv_out, hipStream_t st);
+                              uint32_t alpha, uint32_t *dinv_out, hipStream_t st,
+                              const uint32_t *dinv_in = nullptr);
 // Solves rows [r0, r0 + rows) of Tn X = B in place, every other row's
 // contribution already subtracted; r0 a multiple of 64, rows <=
 // TRSM_LEAF_MAX.  split: operands cut in two (needed once

@@ -138,10 +138,12 @@ template <bool BT>
 __global__ __launch_bounds__(TT) void k_trsm_dscale(const uint32_t *T, int64_t ldt, int unit,
                                                     uint32_t *B, int64_t ldb, int64_t m,
                                                     int64_t n, uint32_t p, double pinv,
-                                                    uint32_t alpha, uint32_t *dinv_out)
+                                                    uint32_t alpha, uint32_t *dinv_out,
+                                                    const uint32_t *dinv_in)
 {
     auto factor = [&](int64_t i, bool write) {
         if (unit) return alpha;
+        if (dinv_in) return mulmod(alpha, dinv_in[i], p, pinv);
         const uint32_t d = inv_mod32(T[i * ldt + i], p);
         if (write && dinv_out) dinv_out[i] = d;
         return mulmod(alpha, d, p, pinv);
@@ -654,18 +656,23 @@ hipError_t launch_trsm_inv_direct(const uint32_t *T, int64_t ldt, int trans, int
 
 hipError_t launch_trsm_dscale(const uint32_t *T, int64_t ldt, int unit, uint32_t *B,
                               int64_t ldb, int bt, int64_t m, int64_t n, uint32_t p,
-                              uint32_t alpha, uint32_t *dinv_out, hipStream_t st)
+                              uint32_t alpha, uint32_t *dinv_out, hipStream_t st,
+                              const uint32_t *dinv_in)
 {
     const double pinv = 1.0 / (double)p;
     if (bt) {
-        // few workgroup rows: each one inverts its 1024 diagonal entries
-        const dim3 grid((unsigned)((m + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(n, 64));
+        // inverting in the pass: few workgroup rows, each one inverts its
+        // 1024 diagonal entries; with the inverses given, enough workgroups
+        // to keep the loads of a large B in flight (four storage rows each)
+        const int64_t gy = dinv_in || unit ? std::max<int64_t>(64, (n + 3) / 4) : 64;
+        const dim3 grid((unsigned)((m + 4 * TT - 1) / (4 * TT)),
+                        (unsigned)std::min<int64_t>(n, std::min<int64_t>(gy, 1024)));
         hipLaunchKernelGGL(k_trsm_dscale<true>, grid, dim3(TT), 0, st, T, ldt, unit, B, ldb, m,
-                           n, p, pinv, alpha, dinv_out);
+                           n, p, pinv, alpha, dinv_out, dinv_in);
     } else {
         const dim3 grid((unsigned)((n + 4 * TT - 1) / (4 * TT)), (unsigned)std::min<int64_t>(m, 64));
         hipLaunchKernelGGL(k_trsm_dscale<false>, grid, dim3(TT), 0, st, T, ldt, unit, B, ldb, m,
-                           n, p, pinv, alpha, dinv_out);
+                           n, p, pinv, alpha, dinv_out, dinv_in);
     }
     return hipGetLastError();
 }

@@ -142,13 +142,16 @@ int ftrsm_run(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, 
     unsigned *bad = (unsigned *)((char *)wsv + tn_bytes + ti_bytes + di_bytes);
     const int lower = (uplo == FF_LOWER) ^ (transT == FF_TRANS);
     // a unit diagonal needs no inverses (dinv stays null for the kernels).
-    // B stored transposed (the LQUP recursion's right-hand solves) and
-    // systems of at most 64 rows take the inverses in the pass that scales
-    // B (one launch instead of two); larger row-major systems, and any
-    // solve that validates (it counts the entries without an inverse), take
-    // them in a pass of their own, one thread per row, and scale B after.
+    // Systems of at most 64 rows, and B stored transposed (the LQUP
+    // recursion's right-hand solves) below 1024 rows, take the inverses in
+    // the pass that scales B (one launch instead of two); the others, and
+    // any solve that validates (it counts the entries without an inverse),
+    // take them in a pass of their own, one thread per row, and scale B
+    // after (a transposed B with the inverses given takes enough workgroups
+    // to keep its loads in flight: at 2048 rows the pass that inverts took
+    // 50 us for 32 MB).
     const bool unit = diag == FF_UNIT;
-    const bool fused = !o.validate && (bt || m <= 64);
+    const bool fused = !o.validate && ((bt && m < 1024) || m <= 64);
     if (fused && (alpha != 1 || !unit))
         FF_HIP_CHECK(launch_trsm_dscale(T, ldt, unit, B, ldb, bt, m, n, p, alpha,
                                         unit ? nullptr : dinv, st));
@@ -179,8 +182,9 @@ int ftrsm_run(uint32_t p, int uplo, int transT, int diag, int64_t m, int64_t n, 
         FF_HIP_CHECK(launch_trsm_inv(Tn, ldn, lower, p, split, Tinv, st));
     }
     if (!fused && (alpha != 1 || !unit)) {
-        if (bt) // (validated above; the pass takes the inverses again)
-            FF_HIP_CHECK(launch_trsm_dscale(T, ldt, unit, B, ldb, 1, m, n, p, alpha, nullptr, st));
+        if (bt)
+            FF_HIP_CHECK(launch_trsm_dscale(T, ldt, unit, B, ldb, 1, m, n, p, alpha, nullptr, st,
+                                            dv));
         else
             FF_HIP_CHECK(launch_trsm_scale(B, ldb, m, n, p, alpha, dv, st));
     }
