@@ -310,11 +310,10 @@ __device__ __forceinline__ bool wait_flag(int *f, bool tight)
 // With m2 > 0 (and nr == W) the last ceil(m2 / 16) workgroups eliminate the
 // m2 rows from g0 on over the window by all nr pivot rows, as rows below
 // them, 16 per workgroup, four in each of the last four waves (those stay to
-// the end anyway: the workgroup's work is then that of a carrying one).
-// The multipliers are G with G T = X, T the
-// panel's U in the window and X those rows' window entries (the caller's
-// right-hand triangular solve for the rows below the panel, fused), stored
-// over X.
+// the end anyway: the workgroup's work is then that of a carrying one).  The
+// multipliers are G with G T = X, T the panel's U in the window and X those
+// rows' window entries (the caller's right-hand triangular solve for the
+// rows below the panel, fused), stored over X.
 //
 // Every workgroup factors the window, which they all read, so the last one
 // to finish (ctr[2], left zero) writes it, and sets *fail to 1 for a zero
