@@ -521,6 +521,49 @@ int ff_plan_query(uint32_t p, int transA, int transB, int64_t m, int64_t n, int6
 
 namespace ff {
 
+int presliced_prepare(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
+                      hipStream_t st, PreSliced *ps)
+{
+    ps->ok = false;
+    if (m <= 0 || n <= 0 || k <= 0 || o.validate) return FF_OK;
+    Plan P;
+    int rc = plan_call(p, m, n, k, o, &P);
+    if (rc) return rc;
+    if (P.levels > 0 || P.path != FF_PATH_INT8 || P.pairing || P.kblock < k) return FF_OK;
+    const int bm = i8_tile(P.tile).bm(), bn = i8_tile(P.tile).bn();
+    const int64_t KP = round_up(k, I8_BK), mp = round_up(m, bm), np = round_up(n, bn);
+    void *ws = nullptr;
+    if ((rc = workspace(st, (size_t)(P.slices * (mp + np) * KP), &ws))) return rc;
+    ps->P = P;
+    ps->Ad = (int8_t *)ws;
+    ps->Bd = ps->Ad + P.slices * mp * KP;
+    ps->plane_a = mp * KP;
+    ps->plane_b = np * KP;
+    ps->rta = bm;
+    ps->rtb = bn;
+    ps->KP = (int)KP;
+    ps->ok = true;
+    return FF_OK;
+}
+
+int presliced_run(const PreSliced &ps, uint32_t p, int64_t m, int64_t n, uint32_t alpha,
+                  uint32_t beta, uint32_t *C, int64_t ldc, hipStream_t st)
+{
+    const Plan &P = ps.P;
+    I8Job J;
+    std::memset(&J, 0, sizeof(J));
+    J.Ad = ps.Ad; J.Bd = ps.Bd; J.a_plane = ps.plane_a; J.b_plane = ps.plane_b;
+    J.C = C; J.ldc = ldc; J.m = (int)m; J.n = (int)n; J.KP = ps.KP; J.s = P.slices;
+    J.p = p; J.beta = beta % p;
+    J.pd = (double)p; J.pinv = 1.0 / (double)p;
+    i8_weights(J, alpha % p, P.bits, 0);
+    J.gm = i8_tile(P.tile).GM;
+    J.tiles_m = (int)(round_up(m, ps.rta) / ps.rta);
+    J.tiles_n = (int)(round_up(n, ps.rtb) / ps.rtb);
+    FF_HIP_CHECK(FF_TIMED(PROF_GEMM, st, launch_i8(P.tile, J, st)));
+    return FF_OK;
+}
+
 int fgemm_call(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t k,
                uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
                int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const ff_opts *opts,

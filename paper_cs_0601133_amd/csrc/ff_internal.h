@@ -319,10 +319,21 @@ hipError_t launch_lqup_panel(uint32_t *A, int64_t lda, int64_t i0, int nr, int64
 // right-hand solve for the rows below, fused).  ctr: the stream's zeroed
 // counter block (word 2, left zero).  Only for p with lqup_panel_fast_ok(p)
 // (centered products exact in binary64).
+// so.ad set (needs m2 > 0, nc > 0, nr == 64): G and the nc carried columns
+// are also written as the INT8 digit planes of the product G times those
+// columns (K = 64; A operand rows m2 with row tile rta, transposed B operand
+// rows nc with row tile rtb; S digits of `bits` bits, planes plane_a and
+// plane_b bytes apart; the digit slicer's layout with KP = 64).
+struct LqupDigits {
+    int8_t *ad = nullptr, *bd = nullptr;
+    int64_t plane_a = 0, plane_b = 0;
+    int rta = 0, rtb = 0, S = 0, bits = 0;
+};
 bool lqup_panel_fast_ok(uint32_t p);
 hipError_t launch_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
                                   int64_t nc, int64_t g0, int m2, uint32_t p, int32_t *fail,
-                                  unsigned *ctr, hipStream_t st);
+                                  unsigned *ctr, hipStream_t st,
+                                  const LqupDigits &so = LqupDigits{});
 // Column exchanges pairs[2j] <-> pairs[2j + 1] in order, rows outside
 // [skip_lo, skip_hi).
 hipError_t launch_lqup_swap(uint32_t *A, int64_t lda, int64_t m, int64_t skip_lo, int64_t skip_hi,

@@ -58,6 +58,27 @@ int fgemm_call(uint32_t p, int transA, int transB, int64_t m, int64_t n, int64_t
                uint32_t alpha, const uint32_t *A, int64_t lda, const uint32_t *B,
                int64_t ldb, uint32_t beta, uint32_t *C, int64_t ldc, const ff_opts *opts,
                void *ws_fixed, size_t ws_fixed_bytes);
+// A product C <- alpha A B + beta C (A m x k, B k x n) whose operands a
+// kernel of the caller writes as INT8 digit planes itself: presliced_prepare
+// tells whether ff_fgemm_ex would run it as one plain INT8 launch (no
+// Winograd level, no digit pairing, K in one pass, no validation) and, if
+// so, takes the workspace for the planes (the stream's fgemm slot, valid
+// until the next fgemm call on the stream) and fills *ps with their layout
+// (the digit slicer's: A rows with row tile rta, B^T rows with row tile
+// rtb, KP padded K, planes plane_a / plane_b bytes apart).  presliced_run
+// then launches the INT8 GEMM on them, exactly as ff_fgemm_ex would after
+// its slicing.
+struct PreSliced {
+    bool ok = false;
+    Plan P;
+    int8_t *Ad = nullptr, *Bd = nullptr;
+    int64_t plane_a = 0, plane_b = 0;
+    int rta = 0, rtb = 0, KP = 0;
+};
+int presliced_prepare(uint32_t p, int64_t m, int64_t n, int64_t k, const ff_opts &o,
+                      hipStream_t st, PreSliced *ps);
+int presliced_run(const PreSliced &ps, uint32_t p, int64_t m, int64_t n, uint32_t alpha,
+                  uint32_t beta, uint32_t *C, int64_t ldc, hipStream_t st);
 // Device address of the static scratch on the current device (noalloc.cpp);
 // noalloc_setup() looks it up once per device.
 int noalloc_setup();

@@ -318,12 +318,29 @@ __device__ __forceinline__ bool wait_flag(int *f, bool tight)
 // Every workgroup factors the window, which they all read, so the last one
 // to finish (ctr[2], left zero) writes it, and sets *fail to 1 for a zero
 // pivot, 2 if a wait gave up.
+//
+// With so.ad set, G and the carried columns are also written as the INT8
+// digit planes of the product that follows (G times those columns, K = 64):
+// the balanced digits of the centered values, in the layout of the digit
+// slicer (G as the A operand, the carried columns as the transposed B
+// operand), so that the product needs no slicing launch.
 template <bool CARRY, bool FOLD>
 __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0,
                                                         int nr, int64_t k, int W, int64_t nc,
                                                         int64_t g0, int m2, uint32_t p,
-                                                        double pinv, int32_t *fail, unsigned *ctr)
+                                                        double pinv, int32_t *fail, unsigned *ctr,
+                                                        LqupDigits so)
 {
+    // digits of canonical u as the byte at dst + d plane, d < so.S
+    auto put_digits = [&](uint32_t u, int8_t *dst, int64_t plane) {
+        const int bits = so.S == 1 ? 8 : so.bits, sh = 32 - bits;
+        int32_t v = center(u, p, (p - 1) / 2);
+        for (int d = 0; d < so.S; ++d) {
+            const int dig = (int)((uint32_t)v << sh) >> sh;
+            v = (v - dig) >> bits;
+            dst[(int64_t)d * plane] = (int8_t)dig;
+        }
+    };
     __shared__ double s_row[PR][PW];                // published rows, window
     __shared__ double s_rowx[CARRY ? PR : 1][64];   // and carried columns
     __shared__ int s_flag[PR];
@@ -494,9 +511,16 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
             const int r = PQ * g + q;
-            if (r < nr && c < xw)
-                A[(i0 + r) * lda + x0 + c] =
-                    mulmod(canon_f64(x[q], pd, pinv, p), s_invS[r], p, pinv);
+            if (r < nr && c < xw) {
+                const uint32_t u = mulmod(canon_f64(x[q], pd, pinv, p), s_invS[r], p, pinv);
+                A[(i0 + r) * lda + x0 + c] = u;
+                if (so.bd) {
+                    // row j of the transposed operand, K index r
+                    const int64_t j = 64 * (int64_t)blockIdx.x + c;
+                    put_digits(u, so.bd + (j / so.rtb) * so.rtb * 64 + (r / 16) * so.rtb * 16 +
+                                      (j % so.rtb) * 16 + r % 16, so.plane_b);
+                }
+            }
         }
     }
     if (below && c < W) {
@@ -504,9 +528,16 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
         const uint32_t f = mulmod(mulmod(s_S[c], s_inv[c], p, pinv), s_invS[nr], p, pinv);
 #pragma unroll
         for (int q = 0; q < PQ; ++q)
-            if (gb + q < m2)
-                A[(g0 + gb + q) * lda + k + c] =
-                    mulmod(canon_f64(x[q], pd, pinv, p), f, p, pinv);
+            if (gb + q < m2) {
+                const uint32_t u = mulmod(canon_f64(x[q], pd, pinv, p), f, p, pinv);
+                A[(g0 + gb + q) * lda + k + c] = u;
+                if (so.ad) {
+                    // row i of the A operand, K index c
+                    const int64_t i = gb + q;
+                    put_digits(u, so.ad + (i / so.rta) * so.rta * 64 + (c / 16) * so.rta * 16 +
+                                      (i % so.rta) * 16 + c % 16, so.plane_a);
+                }
+            }
     }
     if (!s_last) return;
     if (c < W) {
@@ -606,8 +637,11 @@ bool lqup_panel_fast_ok(uint32_t p)
 
 hipError_t launch_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0, int nr, int64_t k, int W,
                                   int64_t nc, int64_t g0, int m2, uint32_t p, int32_t *fail,
-                                  unsigned *ctr, hipStream_t st)
+                                  unsigned *ctr, hipStream_t st, const LqupDigits &so)
 {
+    if (so.ad && (m2 <= 0 || nc <= 0 || !so.bd || nr != 64 || so.S < 1 || so.S > 5 ||
+                  so.rta < 1 || so.rtb < 1 || (so.S > 1 && (so.bits < 2 || so.bits > 8))))
+        return hipErrorInvalidValue;
     if (nr < 1 || nr > PR || W < 1 || W > PW || nc < 0 || m2 < 0 || m2 > (1 << 20) ||
         (m2 > 0 && nr != W) || !fail || !ctr || !lqup_panel_fast_ok(p))
         return hipErrorInvalidValue;
@@ -616,13 +650,14 @@ hipError_t launch_lqup_panel_fast(uint32_t *A, int64_t lda, int64_t i0, int nr, 
     if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
     if (m2 > 0)
         hipLaunchKernelGGL((k_lqup_panel_fast<true, true>), dim3((unsigned)nb), dim3(PT), 0, st, A,
-                           lda, i0, nr, k, W, nc, g0, m2, p, 1.0 / (double)p, fail, ctr);
+                           lda, i0, nr, k, W, nc, g0, m2, p, 1.0 / (double)p, fail, ctr, so);
     else if (nb > 0)
         hipLaunchKernelGGL((k_lqup_panel_fast<true, false>), dim3((unsigned)nb), dim3(PT), 0, st,
-                           A, lda, i0, nr, k, W, nc, g0, 0, p, 1.0 / (double)p, fail, ctr);
+                           A, lda, i0, nr, k, W, nc, g0, 0, p, 1.0 / (double)p, fail, ctr,
+                           LqupDigits{});
     else
         hipLaunchKernelGGL((k_lqup_panel_fast<false, false>), dim3(1), dim3(PT), 0, st, A, lda, i0,
-                           nr, k, W, nc, g0, 0, p, 1.0 / (double)p, fail, ctr);
+                           nr, k, W, nc, g0, 0, p, 1.0 / (double)p, fail, ctr, LqupDigits{});
     return hipGetLastError();
 }
 

@@ -118,6 +118,8 @@ struct Lqup {
     bool fused = false;     // its panels by k_lqup_panel_fast (p small enough)
     int64_t below = 0;      // rows after the next panel whose solve it may fold in
     bool folded = false;    // the last panel solved G T = X for those rows
+    const LqupDigits *digits = nullptr; // the next panel may also write the update's digits
+    bool sliced = false;    // the last panel wrote them
     int32_t *d_fail = nullptr; // set by a panel that contradicts the guess
     unsigned *ctr = nullptr;   // the stream's counter block (fused panels)
     int64_t cus = 256;         // compute units of the device
@@ -172,9 +174,12 @@ int panel_guess(Lqup &c, int64_t a, int64_t b, int64_t *found)
         // caller asks and the panel is 64 rows over a 64-column window, the
         // right-hand solve of the rows below it
         const int m2 = nr == W && W == LQUP_PANEL ? (int)c.below : 0;
-        FF_HIP_CHECK(launch_lqup_panel_fast(c.A, c.lda, a, nr, c.k, W, whole ? 0 : c.n - c.k - W,
-                                            b, m2, c.p, c.d_fail, c.ctr, c.st));
+        const int64_t nc = whole ? 0 : c.n - c.k - W;
+        const bool sliced = c.digits && m2 > 0 && nc > 0;
+        FF_HIP_CHECK(launch_lqup_panel_fast(c.A, c.lda, a, nr, c.k, W, nc, b, m2, c.p, c.d_fail,
+                                            c.ctr, c.st, sliced ? *c.digits : LqupDigits{}));
         c.folded = m2 > 0;
+        c.sliced = sliced;
     } else {
         FF_HIP_CHECK(launch_lqup_panel(c.A, c.lda, a, nr, c.k, W, whole, c.p, c.d_out, c.st,
                                        c.d_fail));
@@ -305,12 +310,35 @@ int blocked(Lqup &c, int64_t a, int64_t b, int64_t *found)
     for (int64_t i = a; i < b; i += LQUP_PANEL) {
         const int64_t e = std::min(i + LQUP_PANEL, b), k0 = c.k, m2 = b - e;
         int64_t r = 0;
+        // when the update after a full panel is one plain INT8 launch, the
+        // panel writes its operands' digit planes (no slicing launch)
+        PreSliced ps;
+        LqupDigits so;
+        const int64_t past = c.n - k0 - LQUP_PANEL;
+        if (e - i == LQUP_PANEL && m2 > 0 && past > 0) {
+            int rc = presliced_prepare(c.p, m2, past, LQUP_PANEL, c.o, c.st, &ps);
+            if (rc) return rc;
+            if (ps.ok && ps.KP == LQUP_PANEL) {
+                so.ad = ps.Ad;
+                so.bd = ps.Bd;
+                so.plane_a = ps.plane_a;
+                so.plane_b = ps.plane_b;
+                so.rta = ps.rta;
+                so.rtb = ps.rtb;
+                so.S = ps.P.slices;
+                so.bits = ps.P.bits;
+                c.digits = &so;
+            }
+        }
         c.below = m2;
         c.folded = false;
+        c.sliced = false;
         int rc = panel(c, i, e, &r);
         c.below = 0;
-        const bool folded = c.folded;
+        c.digits = nullptr;
+        const bool folded = c.folded, sliced = c.sliced;
         c.folded = false;
+        c.sliced = false;
         if (rc) return rc;
         total += r;
         const int64_t nc = c.n - k0;
@@ -323,7 +351,10 @@ int blocked(Lqup &c, int64_t a, int64_t b, int64_t *found)
                 if (rc) return rc;
             }
             if (nc > r) {
-                rc = fgemm_sub(c, m2, nc - r, r, X, c.lda, U + r, c.lda, X + r, c.lda);
+                if (sliced && folded && r == LQUP_PANEL && nc - r == past)
+                    rc = presliced_run(ps, c.p, m2, nc - r, c.p - 1, 1, X + r, c.lda, c.st);
+                else
+                    rc = fgemm_sub(c, m2, nc - r, r, X, c.lda, U + r, c.lda, X + r, c.lda);
                 if (rc) return rc;
             }
         }
