@@ -348,6 +348,11 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
     __shared__ int s_bad, s_last;
     const int tid = threadIdx.x, c = tid % 64;
     const int g = __builtin_amdgcn_readfirstlane(tid / 64);
+    // the wave's block of PQ rows: waves g, g + 4, g + 8, g + 12 share a SIMD
+    // (g mod 4), and a block's work grows with its index, so the blocks are
+    // dealt s, 7 - s, 8 + s, 15 - s to SIMD s: the same work on every SIMD
+    const int wj = g / 4, ws = g % 4;
+    const int gbk = 4 * wj + ((wj & 1) ? 3 - ws : ws);
     const uint32_t half = (p - 1) / 2;
     const double pd = (double)p;
     // gwg: a workgroup of the rows below, whose last four waves hold four of
@@ -356,8 +361,8 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
     const int ng = (m2 + 15) / 16;
     const bool gwg = FOLD && (int)blockIdx.x >= (int)gridDim.x - ng;
     const bool xc = CARRY && !gwg;
-    const bool below = gwg && g >= PG - 4;
-    const int gb = 16 * ((int)blockIdx.x - ((int)gridDim.x - ng)) + PQ * (g - (PG - 4));
+    const bool below = gwg && gbk >= PG - 4;
+    const int gb = 16 * ((int)blockIdx.x - ((int)gridDim.x - ng)) + PQ * (gbk - (PG - 4));
     const int64_t x0 = k + W + 64 * (int64_t)blockIdx.x;
     const int64_t xleft = nc - 64 * (int64_t)blockIdx.x;
     const int xw = xc ? (int)(xleft < 64 ? xleft : 64) : 0;
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
     double v[PQ], x[PQ];
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
-        const int r = PQ * g + q;
+        const int r = PQ * gbk + q;
         uint32_t u = 0, ux = 0;
         if (r < nr && c < W) u = A[(i0 + r) * lda + k + c];
         if (xc && r < nr && c < xw) ux = A[(i0 + r) * lda + x0 + c];
@@ -376,7 +381,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
     if (tid < PR) s_flag[tid] = 0;
     if (tid == 0) s_bad = 0;
     __syncthreads();
-    if (g == 0) {
+    if (gbk == 0) {
         s_row[0][c] = v[0];
         if (xc) s_rowx[0][c] = x[0];
         __hip_atomic_store(&s_flag[0], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -387,16 +392,16 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
     // the panel take every pivot row, the panel's own rows all but the last
     const int steps = gwg ? nr : nr - 1;
     for (int r = 0; r < steps; ++r) {
-        const bool done = PQ * g + PQ - 1 <= r; // this wave's panel rows are finished
+        const bool done = PQ * gbk + PQ - 1 <= r; // this wave's panel rows are finished
         if (done && !below) break;
         const int gn = (r + 1) / PQ, qn = (r + 1) % PQ;
         double y, yx = 0.0;
-        if (g == gn && qn != 0) {
+        if (gbk == gn && qn != 0) {
             // row r is this wave's row qn - 1
             y = qn == 1 ? v[0] : qn == 2 ? v[1] : v[2];
             if (xc) yx = qn == 1 ? x[0] : qn == 2 ? x[1] : x[2];
         } else {
-            if (!gave_up) gave_up = !wait_flag(&s_flag[r], g == gn);
+            if (!gave_up) gave_up = !wait_flag(&s_flag[r], gbk == gn);
             y = s_row[r][c];
             if (xc) yx = s_rowx[r][c];
         }
@@ -433,7 +438,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
                 s_row[r + 1][c] = w;
                 if (WX) s_rowx[r + 1][c] = wx;
             };
-            if (g == gn) {
+            if (gbk == gn) {
                 // row r + 1 (this wave's row qn) first, at raised priority:
                 // its entries go out before the rows after it are updated,
                 // the flag after them
@@ -510,7 +515,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
     if (xc) {
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
-            const int r = PQ * g + q;
+            const int r = PQ * gbk + q;
             if (r < nr && c < xw) {
                 const uint32_t u = mulmod(canon_f64(x[q], pd, pinv, p), s_invS[r], p, pinv);
                 A[(i0 + r) * lda + x0 + c] = u;
@@ -544,7 +549,7 @@ __global__ __launch_bounds__(PT) void k_lqup_panel_fast(uint32_t *A, int64_t lda
         const uint32_t colf = c < nr ? mulmod(s_S[c], s_inv[c], p, pinv) : 0u;
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
-            const int r = PQ * g + q;
+            const int r = PQ * gbk + q;
             if (r >= nr) continue;
             const uint32_t f = c < r ? mulmod(colf, s_invS[r], p, pinv) : s_invS[r];
             A[(i0 + r) * lda + k + c] = mulmod(canon_f64(v[q], pd, pinv, p), f, p, pinv);
